@@ -1,0 +1,506 @@
+"""FP64 CPU oracle of the learned-codec hot path.
+
+TEST INFRASTRUCTURE ONLY: this package may be imported by ``tests/``, by
+``__graft_entry__.smoke()`` and by the CPU-baseline leg of ``bench.py``, and
+by nothing else.  It shares no code with ``paper_2208_01641_amd`` (the HIP
+library): neither imports the other.  The only module both use is ``synth``
+(seeded inputs, none of the method's arithmetic).
+
+The numerical primitives live in ``lic_oracle.c`` (plain double-precision
+loops); this module strings them together into the codecs of the paper:
+
+  * factorized prior (Section III.A, Fig. 1): x -> g_a -> y -> quantise with
+    a per-channel offset -> entropy code with per-channel tables;
+  * scale hyperprior (Section III.B, Fig. 1): additionally z = h_a(|y|) is
+    quantised and coded, and h_s(z_hat) gives the scales whose table index
+    selects the Gaussian table each element of y is coded with.
+
+The architecture details the paper leaves to its cited models (layer shapes,
+GDN, quantiser, tables, rANS, bitstream) follow the readings listed in the
+design notes; each function below states the one it implements.
+
+Parity status: pinned by ``tests/test_oracle_*.py`` (brute force, closed
+forms, identities, round trips).  No function here is "parity unpinned".
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import struct
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "lic_oracle.c")
+_SO = os.path.join(_HERE, "liblic_oracle.so")
+
+NSYM = 129          # symbols -64..64
+SYM_MIN = -64
+SYM_MAX = 64
+PREC = 16           # frequency precision, totals 2^16
+RANS_L = 1 << 23
+
+
+def build(force: bool = False) -> str:
+    """Compile lic_oracle.c with gcc (plain -O2, no fast-math, OpenMP)."""
+    if force or not os.path.exists(_SO) or os.path.getmtime(_SO) < os.path.getmtime(_SRC):
+        tmp = _SO + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
+                               "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _SO)
+    return _SO
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        L = ctypes.CDLL(build())
+        d, i, l = ctypes.c_double, ctypes.c_int, ctypes.c_long
+        P = ctypes.c_void_p
+        L.or_conv2d_at.restype = d
+        L.or_conv2d_at.argtypes = [P, i, i, i, P, P, i, i, i, i, i, i]
+        L.or_conv2d.restype = None
+        L.or_conv2d.argtypes = [P, i, i, i, P, P, i, i, i, i, P, i, i]
+        L.or_deconv2d_at.restype = d
+        L.or_deconv2d_at.argtypes = [P, i, i, i, P, P, i, i, i, i, i, i, i]
+        L.or_deconv2d.restype = None
+        L.or_deconv2d.argtypes = [P, i, i, i, P, P, i, i, i, i, P, i, i]
+        L.or_gdn.restype = None
+        L.or_gdn.argtypes = [P, i, l, P, P, i, P]
+        L.or_density_logit.restype = d
+        L.or_density_logit.argtypes = [P, d]
+        L.or_density_cdf.restype = d
+        L.or_density_cdf.argtypes = [P, d]
+        L.or_density_median.restype = d
+        L.or_density_median.argtypes = [P]
+        L.or_pmf_factorized.restype = None
+        L.or_pmf_factorized.argtypes = [P, d, P]
+        L.or_pmf_gaussian.restype = None
+        L.or_pmf_gaussian.argtypes = [d, P]
+        L.or_quantize_pmf.restype = None
+        L.or_quantize_pmf.argtypes = [P, P]
+        L.or_scale_table.restype = None
+        L.or_scale_table.argtypes = [P]
+        L.or_scale_index.restype = i
+        L.or_scale_index.argtypes = [P, d]
+        L.or_rans_encode.restype = l
+        L.or_rans_encode.argtypes = [P, P, l, P, P, l]
+        L.or_rans_decode.restype = i
+        L.or_rans_decode.argtypes = [P, l, P, l, P, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ----------------------------------------------------------------------------
+# neural-transform primitives (single image, C x H x W, float64)
+# ----------------------------------------------------------------------------
+def conv2d(x, w, b, s: int, p: int) -> np.ndarray:
+    """Strided convolution with zero padding p; w is [C_out, C_in, k, k]."""
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    Co, Ci, k, _ = w.shape
+    assert Ci == C
+    Ho = (H + 2 * p - k) // s + 1
+    Wo = (W + 2 * p - k) // s + 1
+    out = np.empty((Co, Ho, Wo), np.float64)
+    lib().or_conv2d(_p(x), C, H, W, _p(w), None if b is None else _p(b), Co, k, s, p, _p(out), Ho, Wo)
+    return out
+
+
+def conv2d_at(x, w, b, s: int, p: int, o: int, i: int, j: int) -> float:
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    return lib().or_conv2d_at(_p(x), C, H, W, _p(w), None if b is None else _p(b), w.shape[2], s, p, o, i, j)
+
+
+def deconv2d(x, w, b, s: int, p: int, op: int) -> np.ndarray:
+    """Transposed convolution; w is [C_in, C_out, k, k]; H_out = (H-1)s - 2p + k + op."""
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    Ci, Co, k, _ = w.shape
+    assert Ci == C
+    Ho = (H - 1) * s - 2 * p + k + op
+    Wo = (W - 1) * s - 2 * p + k + op
+    out = np.empty((Co, Ho, Wo), np.float64)
+    lib().or_deconv2d(_p(x), C, H, W, _p(w), None if b is None else _p(b), Co, k, s, p, _p(out), Ho, Wo)
+    return out
+
+
+def deconv2d_at(x, w, b, s: int, p: int, o: int, i: int, j: int) -> float:
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    return lib().or_deconv2d_at(_p(x), C, H, W, _p(w), None if b is None else _p(b), w.shape[1], w.shape[2],
+                                s, p, o, i, j)
+
+
+def gdn(x, beta, gamma, inverse: bool = False) -> np.ndarray:
+    """GDN y_i = x_i / sqrt(beta_i + sum_j gamma_ij x_j^2); IGDN multiplies instead."""
+    x = _f64(x)
+    C = x.shape[0]
+    HW = int(np.prod(x.shape[1:]))
+    out = np.empty_like(x)
+    lib().or_gdn(_p(x), C, HW, _p(_f64(beta)), _p(_f64(gamma)), int(inverse), _p(out))
+    return out
+
+
+def relu(x):
+    return np.maximum(x, 0.0)
+
+
+# ----------------------------------------------------------------------------
+# quantiser and entropy parameters
+# ----------------------------------------------------------------------------
+def rne(v):
+    """Round half to even (numpy's rint under the default rounding mode)."""
+    return np.rint(v)
+
+
+def quantize(v, mu):
+    """sym = clamp(rne(v - mu), -64, 64); v_hat = sym + mu.  mu broadcasts per channel."""
+    d = np.asarray(v, np.float64) - np.asarray(mu, np.float64)
+    sym = np.clip(rne(d), SYM_MIN, SYM_MAX)
+    return sym.astype(np.int32), sym + np.asarray(mu, np.float64)
+
+
+def quantize_f32(v32, mu32):
+    """The same decision taken in single precision: rne(float32(v - mu))."""
+    d = np.asarray(v32, np.float32) - np.asarray(mu32, np.float32)
+    return np.clip(np.rint(d), SYM_MIN, SYM_MAX).astype(np.int32)
+
+
+def scale_table() -> np.ndarray:
+    t = np.empty(64, np.float64)
+    lib().or_scale_table(_p(t))
+    return t
+
+
+def scale_index(s, t=None) -> np.ndarray:
+    """idx = #{k in [0,62] : t_k < max(s, t_0)} elementwise."""
+    t = scale_table() if t is None else t
+    s = np.asarray(s, np.float64)
+    s = np.maximum(s, t[0])
+    return np.sum(t[None, :63] < s.reshape(-1, 1), axis=1).reshape(s.shape).astype(np.int32)
+
+
+def scales_from_hs(v, hs_out: int) -> np.ndarray:
+    """Output activation of h_s: exp (hs_out=1) or ReLU (hs_out=0)."""
+    v = np.asarray(v, np.float64)
+    return np.exp(v) if hs_out == 1 else np.maximum(v, 0.0)
+
+
+def scale_index_f32(v32, hs_out: int) -> np.ndarray:
+    """The scale-index decision taken in single precision.
+
+    exp output: exp(v) > t_k  <=>  v > ln t_k, so the comparison is made on
+    v against float32(ln t_k).  ReLU output: float32(max(v, 0)) against the
+    float32 table after the clamp to t_0.
+    """
+    t = scale_table()
+    v = np.asarray(v32, np.float32).reshape(-1, 1)
+    if hs_out == 1:
+        lt = np.log(t[:63]).astype(np.float32)
+        cnt = np.sum(lt[None, :] < v, axis=1)
+    else:
+        t32 = t.astype(np.float32)
+        s = np.maximum(np.maximum(v, np.float32(0.0)), t32[0])
+        cnt = np.sum(t32[None, :63] < s, axis=1)
+    return cnt.reshape(np.shape(v32)).astype(np.int32)
+
+
+def density_logit(prm, x: float) -> float:
+    return lib().or_density_logit(_p(_f64(prm)), float(x))
+
+
+def density_cdf(prm, x: float) -> float:
+    return lib().or_density_cdf(_p(_f64(prm)), float(x))
+
+
+def density_median(prm) -> float:
+    return lib().or_density_median(_p(_f64(prm)))
+
+
+def pmf_factorized(prm, mu: float) -> np.ndarray:
+    p = np.empty(NSYM, np.float64)
+    lib().or_pmf_factorized(_p(_f64(prm)), float(mu), _p(p))
+    return p
+
+
+def pmf_gaussian(t: float) -> np.ndarray:
+    p = np.empty(NSYM, np.float64)
+    lib().or_pmf_gaussian(float(t), _p(p))
+    return p
+
+
+def quantize_pmf(p) -> np.ndarray:
+    p = _f64(p)
+    f = np.empty(NSYM, np.uint32)
+    lib().or_quantize_pmf(_p(p), _p(f))
+    return f
+
+
+# ----------------------------------------------------------------------------
+# rANS
+# ----------------------------------------------------------------------------
+def rans_encode(sym, tab, freq) -> bytes:
+    """Alphabet indices sym (0..128), table id per symbol, freq [ntab, 129]."""
+    sym = np.ascontiguousarray(sym, np.int32).ravel()
+    tab = np.ascontiguousarray(tab, np.int32).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    n = sym.size
+    cap = 4 * n + 64
+    out = np.empty(cap, np.uint8)
+    ln = lib().or_rans_encode(_p(sym), _p(tab), n, _p(freq), _p(out), cap)
+    if ln < 0:
+        raise RuntimeError("rANS output overflow")
+    return out[:ln].tobytes()
+
+
+def rans_decode(data: bytes, tab, freq, n: int) -> np.ndarray:
+    tab = np.ascontiguousarray(tab, np.int32).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    buf = np.frombuffer(data, np.uint8).copy() if len(data) else np.zeros(1, np.uint8)
+    sym = np.empty(n, np.int32)
+    rc = lib().or_rans_decode(_p(buf), len(data), _p(tab), n, _p(freq), _p(sym))
+    if rc != 0:
+        raise ValueError("corrupt rANS stream (code %d)" % rc)
+    return sym
+
+
+def fnv1a32(data: bytes) -> int:
+    h = 2166136261
+    for byte in data:
+        h ^= byte
+        h = (h * 16777619) & 0xFFFFFFFF
+    return h
+
+
+# ----------------------------------------------------------------------------
+# the codec
+# ----------------------------------------------------------------------------
+def pad64(x):
+    """Zero-pad a C x H x W image at the bottom and right to multiples of 64."""
+    C, H, W = x.shape
+    Hp, Wp = 64 * math.ceil(H / 64), 64 * math.ceil(W / 64)
+    out = np.zeros((C, Hp, Wp), np.float64)
+    out[:, :H, :W] = x
+    return out
+
+
+class Model:
+    """Parameters of one codec plus the entropy tables derived from them.
+
+    kind 0 = factorized prior, 1 = scale hyperprior.  hs_out selects the
+    output activation of h_s (1 = exp, 0 = ReLU).
+    """
+
+    def __init__(self, params, kind: int, N: int, M: int, blob: bytes = b"", hs_out: int = 1):
+        self.P = {k: np.asarray(v) for k, v in params.items()}
+        self.kind, self.N, self.M, self.hs_out = kind, N, M, hs_out
+        self.model_id = fnv1a32(blob) if blob else 0
+        dens = self.P["eb.density"]
+        # channel offsets: FP64 bisection, rounded to float32
+        self.medians = np.array([np.float32(density_median(dens[c])) for c in range(dens.shape[0])],
+                                np.float32)
+        self.freq_fact = np.stack([quantize_pmf(pmf_factorized(dens[c], float(self.medians[c])))
+                                   for c in range(dens.shape[0])])
+        self.t = scale_table()
+        self.freq_gauss = np.stack([quantize_pmf(pmf_gaussian(self.t[k])) for k in range(64)])
+
+    # ---- transforms (one image, C x H x W) ----
+    def g_a(self, x, keep=None):
+        P = self.P
+        h = x
+        for i in range(4):
+            h = conv2d(h, P[f"ga{i}.w"], P[f"ga{i}.b"], 2, 2)
+            if i < 3:
+                h = gdn(h, P[f"ga{i}.beta"], P[f"ga{i}.gamma"])
+            if keep is not None:
+                keep.append(h)
+        return h
+
+    def g_s(self, y, keep=None):
+        P = self.P
+        h = y
+        for i in range(4):
+            h = deconv2d(h, P[f"gs{i}.w"], P[f"gs{i}.b"], 2, 2, 1)
+            if i < 3:
+                h = gdn(h, P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
+            if keep is not None:
+                keep.append(h)
+        return h
+
+    def h_a(self, y, keep=None):
+        P = self.P
+        h = relu(conv2d(np.abs(y), P["ha0.w"], P["ha0.b"], 1, 1))
+        if keep is not None: keep.append(h)
+        h = relu(conv2d(h, P["ha1.w"], P["ha1.b"], 2, 2))
+        if keep is not None: keep.append(h)
+        h = conv2d(h, P["ha2.w"], P["ha2.b"], 2, 2)
+        if keep is not None: keep.append(h)
+        return h
+
+    def h_s(self, zhat, keep=None):
+        """Pre-activation output v of h_s; scales = exp(v) or ReLU(v)."""
+        P = self.P
+        h = relu(deconv2d(zhat, P["hs0.w"], P["hs0.b"], 2, 2, 1))
+        if keep is not None: keep.append(h)
+        h = relu(deconv2d(h, P["hs1.w"], P["hs1.b"], 2, 2, 1))
+        if keep is not None: keep.append(h)
+        h = conv2d(h, P["hs2.w"], P["hs2.b"], 1, 1)
+        if keep is not None: keep.append(h)
+        return h
+
+    # ---- entropy coding helpers (HWC raster, channel fastest) ----
+    @staticmethod
+    def slice_rows(Hy: int, S: int):
+        return [(s * Hy // S, (s + 1) * Hy // S) for s in range(S)]
+
+    def _code_factorized(self, sym_chw):
+        C = sym_chw.shape[0]
+        hwc = np.transpose(sym_chw, (1, 2, 0))
+        tab = np.broadcast_to(np.arange(C, dtype=np.int32), hwc.shape)
+        return hwc.ravel() - SYM_MIN, np.ascontiguousarray(tab).ravel()
+
+    # ---- codec ----
+    def encode(self, x, S: int = 1):
+        """x: 3 x H x W in [0,1].  Returns (bitstream bytes, intermediates)."""
+        _, H, W = x.shape
+        xp = pad64(np.asarray(x, np.float64))
+        inter = {"ga": []}
+        y = self.g_a(xp, inter["ga"])
+        inter["y"] = y
+        M, Hy, Wy = y.shape
+        payloads = []
+        if self.kind == 0:
+            sym_y, yhat = quantize(y, self.medians[:, None, None])
+            inter["sym_y"] = sym_y
+            syms, tabs = self._code_factorized(sym_y)
+            syms = syms.reshape(Hy, Wy * M)
+            tabs = tabs.reshape(Hy, Wy * M)
+            ys = [rans_encode(syms[a:b], tabs[a:b], self.freq_fact) for a, b in self.slice_rows(Hy, S)]
+        else:
+            inter["ha"] = []
+            z = self.h_a(y, inter["ha"])
+            inter["z"] = z
+            sym_z, zhat = quantize(z, self.medians[:, None, None])
+            inter["sym_z"] = sym_z
+            v = self.h_s(zhat, inter.setdefault("hs", []))
+            inter["v"] = v
+            idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+            inter["idx"] = idx
+            sym_y, yhat = quantize(y, 0.0)
+            inter["sym_y"] = sym_y
+            zs, zt = self._code_factorized(sym_z)
+            payloads.append(rans_encode(zs, zt, self.freq_fact))
+            ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
+            ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
+            ys = [rans_encode(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+        inter["yhat"] = yhat
+        bits = pack_container(self.kind, self.hs_out, S, H, W, self.N, self.M, self.model_id,
+                              payloads[0] if self.kind == 1 else None, ys)
+        return bits, inter
+
+    def decode(self, bits: bytes, keep=None):
+        hdr = parse_container(bits)
+        if hdr["model_id"] != self.model_id or hdr["kind"] != self.kind:
+            raise ValueError("bitstream was made by another model")
+        H, W, S = hdr["H"], hdr["W"], hdr["S"]
+        Hy, Wy = 4 * math.ceil(H / 64), 4 * math.ceil(W / 64)
+        M, N = self.M, self.N
+        inter = {} if keep is None else keep
+        if self.kind == 0:
+            yhat_hwc = np.empty((Hy, Wy, M), np.float64)
+            for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
+                tab = np.broadcast_to(np.arange(M, dtype=np.int32), (b - a, Wy, M))
+                sym = rans_decode(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
+                yhat_hwc[a:b] = sym + SYM_MIN + self.medians[None, None, :].astype(np.float64)
+        else:
+            Hz, Wz = Hy // 4, Wy // 4
+            tab = np.broadcast_to(np.arange(N, dtype=np.int32), (Hz, Wz, N))
+            sz = rans_decode(hdr["z"], tab, self.freq_fact, Hz * Wz * N).reshape(Hz, Wz, N) + SYM_MIN
+            zhat = np.transpose(sz, (2, 0, 1)) + self.medians[:, None, None].astype(np.float64)
+            inter["sym_z"] = np.transpose(sz, (2, 0, 1))
+            v = self.h_s(zhat)
+            idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+            inter["idx"] = idx
+            idx_hwc = np.transpose(idx, (1, 2, 0))
+            yhat_hwc = np.empty((Hy, Wy, M), np.float64)
+            for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
+                sym = rans_decode(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
+                yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
+        yhat = np.transpose(yhat_hwc, (2, 0, 1))
+        inter["yhat"] = yhat
+        xr = self.g_s(yhat)
+        inter["x_pre"] = xr
+        return np.clip(xr, 0.0, 1.0)[:, :H, :W], inter
+
+
+# ----------------------------------------------------------------------------
+# bitstream container: "LICS", u8 version, u8 kind, u8 flags (bit 0 = exp
+# output of h_s), u8 S, u16 H, u16 W, u16 N, u16 M, u32 model id,
+# [u32 len_z], S x u32 len_y, payloads z, y_0 .. y_{S-1}; little-endian.
+# ----------------------------------------------------------------------------
+def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys) -> bytes:
+    out = bytearray(b"LICS")
+    out += struct.pack("<BBBBHHHHI", 1, kind, hs_out & 1, S, H, W, N, M, model_id)
+    if kind == 1:
+        out += struct.pack("<I", len(z))
+    out += struct.pack(f"<{S}I", *[len(y) for y in ys])
+    if kind == 1:
+        out += z
+    for y in ys:
+        out += y
+    return bytes(out)
+
+
+def parse_container(bits: bytes) -> dict:
+    if len(bits) < 20 or bits[:4] != b"LICS":
+        raise ValueError("not a LICS bitstream")
+    ver, kind, flags, S, H, W, N, M, mid = struct.unpack_from("<BBBBHHHHI", bits, 4)
+    if ver != 1 or kind not in (0, 1) or S < 1 or H == 0 or W == 0:
+        raise ValueError("bad header")
+    pos = 20
+    nlen = S + (1 if kind == 1 else 0)
+    if len(bits) < pos + 4 * nlen:
+        raise ValueError("truncated header")
+    lens = struct.unpack_from(f"<{nlen}I", bits, pos)
+    pos += 4 * nlen
+    if pos + sum(lens) != len(bits):
+        raise ValueError("length mismatch")
+    hdr = {"kind": kind, "hs_out": flags & 1, "S": S, "H": H, "W": W, "N": N, "M": M, "model_id": mid}
+    if kind == 1:
+        hdr["z"] = bits[pos:pos + lens[0]]
+        pos += lens[0]
+        lens = lens[1:]
+    ys = []
+    for ln in lens:
+        ys.append(bits[pos:pos + ln])
+        pos += ln
+    hdr["y"] = ys
+    return hdr
+
+
+def psnr(x, xr) -> float:
+    mse = float(np.mean((np.asarray(x, np.float64) - np.asarray(xr, np.float64)) ** 2))
+    return float("inf") if mse == 0 else 10.0 * math.log10(1.0 / mse)
+
+
+def bpp(nbytes: int, H: int, W: int) -> float:
+    return 8.0 * nbytes / (H * W)
