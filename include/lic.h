@@ -1,0 +1,184 @@
+/*
+ * lic.h - C ABI of the MI355X learned-image-codec library.
+ *
+ * The library implements the streaming architecture for learned image codecs
+ * of Lin, Sun and Katto (arXiv 2208.01641): an encoder takes frames and
+ * produces bitstreams ("strings"), a decoder takes bitstreams and produces
+ * frames (Section III.A-B).  The neural transforms (g_a, h_a, h_s, g_s with
+ * GDN/IGDN, quantisation and the scale-table index) run as HIP kernels on
+ * one GPU; rANS entropy coding runs on CPU worker threads; the two are
+ * overlapped in a multi-stage pipeline with pooled, pinned host buffers
+ * (Sections III.A-D: 2-stage encoder, 2-stage factorized decoder, 4-stage
+ * hyperprior decoder CPU1-GPU1-CPU2-GPU2, zero-copy memory with a toggle,
+ * memory pooling).  Every frame is an independent keyframe (Section VI).
+ *
+ * Conventions
+ *   - Every call returns a lic_status (0 = success, negative = error); no
+ *     exception or abort crosses the ABI.  codec_last_error() gives a message.
+ *   - The caller owns every input and output buffer; the codec owns its HIP
+ *     streams, device memory pool, pinned host slots, threads and tables.
+ *   - A codec handle is used by one calling thread at a time.
+ *   - Images are n x 3 x H x W float32 (NCHW) in [0, 1].  H and W need not be
+ *     multiples of 64: frames are zero-padded at the bottom/right to the next
+ *     multiple of 64 inside the codec and decoded frames are cropped back.
+ *   - Pointers flagged "is_device" are HIP device pointers on the codec's
+ *     device; the caller must have completed all work producing them before
+ *     the call (the library runs on its own streams).
+ */
+#ifndef LIC_H
+#define LIC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct codec codec_t;
+
+typedef enum {
+    LIC_OK = 0,
+    LIC_E_ARG = -1,       /* invalid argument or unsupported configuration        */
+    LIC_E_NOMEM = -2,     /* host or device allocation failed (at create only)    */
+    LIC_E_HIP = -3,       /* a HIP runtime call failed                            */
+    LIC_E_CORRUPT = -4,   /* malformed, truncated or inconsistent bitstream       */
+    LIC_E_SMALLBUF = -5,  /* output capacity too small; required sizes returned   */
+    LIC_E_BUDGET = -6,    /* request exceeds the configured limits (size/memory)  */
+    LIC_E_STATE = -7,     /* call not valid in the codec's current state          */
+    LIC_E_MODEL = -8      /* weight blob or bitstream belongs to another model    */
+} lic_status;
+
+enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1 };
+enum { LIC_PREC_FP32 = 0 };
+enum { LIC_HS_RELU = 0, LIC_HS_EXP = 1 };
+
+/* Creation parameters.  Fill with codec_default_config() first. */
+typedef struct {
+    uint32_t struct_size;      /* sizeof(codec_config), for ABI versioning           */
+    int32_t  kind;             /* LIC_KIND_*: factorized prior [1] or hyperprior [2] */
+    int32_t  N, M;             /* transform / latent channels (128/192 or 192/320)   */
+    int32_t  precision;        /* LIC_PREC_FP32                                      */
+    int32_t  hs_out;           /* output activation of h_s: LIC_HS_EXP or _RELU      */
+    int32_t  gs_mode;          /* 0: full synthesis transform                        */
+    int32_t  y_slices;         /* S >= 1 independent rANS streams for y (row bands)  */
+    int32_t  entropy_threads;  /* CPU entropy worker threads (paper: 3 and 10)       */
+    int32_t  zero_copy;        /* 1: kernels read/write mapped pinned host slots;    */
+                               /* 0: device buffers plus async copies (Sec. III.D)   */
+    int32_t  max_in_flight;    /* frames in flight = pooled slots per pipeline       */
+    int32_t  max_h, max_w;     /* largest frame the pools are sized for              */
+    int32_t  max_batch;        /* frames per GPU launch (1 = per-frame)              */
+    uint64_t hbm_budget_bytes; /* device memory the pools may take (0 = no limit)    */
+    int32_t  hip_device;       /* HIP device ordinal                                 */
+} codec_config;
+
+/* Defaults: hyperprior, N=128, M=192, FP32, exp output, S=8, 8 entropy
+ * threads, zero_copy=0, 6 frames in flight, 1088x1920 max, batch 1. */
+void codec_default_config(codec_config* cfg);
+
+/* Creates a codec from a "LICW" weight blob (see DESIGN notes: per-layer
+ * float32 weights in PyTorch layouts, GDN beta/gamma, float64 raw density
+ * parameters).  The blob's kind/N/M must match cfg (else LIC_E_MODEL).  The
+ * blob is copied; the caller may free it after the call.  Builds all entropy
+ * tables, uploads packed weights, allocates every pool.  *out = NULL on error. */
+int codec_create(const codec_config* cfg, const void* weight_blob, size_t blob_len, codec_t** out);
+
+/* Encodes n frames (pipelined).  x: n x 3 x H x W float32, host or device.
+ * Bitstreams are written back to back into out[0..cap); lens[i] receives the
+ * length of frame i.  On LIC_E_SMALLBUF nothing is written to out and lens[]
+ * holds each frame's size. */
+int codec_encode(codec_t* c, const float* x, int n, int H, int W, int is_device,
+                 uint8_t* out, size_t cap, size_t* lens);
+
+/* Decodes n bitstreams stored back to back in bits (lengths lens[0..n)).
+ * All frames must share one size; *H, *W receive it.  x_hat receives
+ * n x 3 x H x W float32 (host or device) and holds cap_elems floats. */
+int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n,
+                 float* x_hat, size_t cap_elems, int is_device, int* H, int* W);
+
+/* Encoder chained into the decoder per frame (one pipeline: GPU encode, CPU
+ * encode, CPU1, GPU1, CPU2, GPU2 for the hyperprior).  Writes the bitstreams
+ * like codec_encode and the reconstructions like codec_decode. */
+int codec_encode_decode(codec_t* c, const float* x, int n, int H, int W, int is_device,
+                        uint8_t* bits, size_t cap, size_t* lens, float* x_hat);
+
+/* Per-frame latency (milliseconds, admission to result ready) of the last
+ * encode / decode / encode_decode call, in frame order.  Returns the count
+ * written (at most max). */
+int codec_last_latencies(const codec_t* c, double* ms, int max);
+
+/* JSON statistics of the last call (frames/s, p50/p99, per-stage busy time). */
+int codec_get_stats(const codec_t* c, char* buf, size_t cap);
+
+/* Drains in-flight work, joins threads, frees pools.  NULL-safe. */
+void codec_destroy(codec_t* c);
+
+/* Message describing the last error on this handle (valid until the next
+ * call on it).  With c == NULL: the last error of a failed codec_create. */
+const char* codec_last_error(const codec_t* c);
+
+/* ------------------------------------------------------------------------ */
+/* Stage-level entry points: one layer of the transforms on device buffers,  */
+/* run synchronously on the codec's stream.  For parity checks and           */
+/* profiling.  H, W are the original frame size; the layer's tensor sizes    */
+/* follow from the 64-multiple padded size Hp x Wp (latents Hp/16 x Wp/16,   */
+/* hyper-latents Hp/64 x Wp/64).  All tensors are NHWC except images.        */
+/*                                                                          */
+/*  layer          in                         out                aux         */
+/*  LIC_GA0..GA2   ga0: image NCHW f32         NHWC f32           -           */
+/*  LIC_GA3        NHWC f32                    y NHWC f32         sym_y int8  */
+/*  LIC_HA0..HA1   NHWC f32 (ha0 takes y)      NHWC f32           -           */
+/*  LIC_HA2        NHWC f32                    z NHWC f32         sym_z int8  */
+/*  LIC_HS0        sym_z int8 NHWC             NHWC f32           -           */
+/*  LIC_HS1        NHWC f32                    NHWC f32           -           */
+/*  LIC_HS2        NHWC f32                    idx uint8 NHWC     v f32 / NULL*/
+/*  LIC_GS0        sym_y int8 NHWC             NHWC f32           -           */
+/*  LIC_GS1..GS2   NHWC f32                    NHWC f32           -           */
+/*  LIC_GS3        NHWC f32                    image NCHW f32 (cropped,      */
+/*                                             clamped)           pre-clamp   */
+/*                                             image n x 3 x Hp x Wp / NULL   */
+/* ------------------------------------------------------------------------ */
+enum {
+    LIC_GA0 = 0, LIC_GA1, LIC_GA2, LIC_GA3,
+    LIC_HA0, LIC_HA1, LIC_HA2,
+    LIC_HS0, LIC_HS1, LIC_HS2,
+    LIC_GS0, LIC_GS1, LIC_GS2, LIC_GS3,
+    LIC_NUM_LAYERS
+};
+int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
+                    const void* in, void* out, void* aux);
+
+/* Entropy tables the codec built at create (host copies, for checking):
+ * which 0 = factorized tables [C][129] (C = N for the hyperprior's z, M for
+ * the factorized prior's y), 1 = Gaussian tables [64][129].  Returns the
+ * number of uint32 written, or LIC_E_SMALLBUF.  Channel offsets (medians,
+ * float32) via codec_medians. */
+long codec_tables(const codec_t* c, int which, uint32_t* freq, size_t cap);
+long codec_medians(const codec_t* c, float* mu, size_t cap);
+
+/* ------------------------------------------------------------------------ */
+/* Host entropy primitives (no GPU needed).                                 */
+/* ------------------------------------------------------------------------ */
+/* Byte-wise rANS (32-bit state, L = 2^23, 16-bit frequencies).  sym holds
+ * alphabet indices 0..128 (value + 64), tab the table of each symbol, freq
+ * is [ntab][129].  Returns the stream length, or LIC_E_SMALLBUF. */
+long lic_rans_encode(const uint8_t* sym, const uint8_t* tab, long n,
+                     const uint32_t* freq, int ntab, uint8_t* out, size_t cap);
+/* Returns LIC_OK, or LIC_E_CORRUPT if the stream is truncated or does not
+ * end in the initial state with every byte consumed. */
+int  lic_rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n,
+                     const uint32_t* freq, int ntab, uint8_t* sym);
+/* FNV-1a 32-bit hash (the model id carried in every bitstream). */
+uint32_t lic_fnv1a(const void* data, size_t len);
+/* Entropy tables a codec would build from this weight blob, computed on the
+ * host without a GPU: which 0 = factorized [C][129], 1 = Gaussian [64][129].
+ * The float32 channel offsets (medians of the factorized densities) go to mu
+ * when mu != NULL.  Returns the number of uint32 written, or a negative
+ * lic_status (LIC_E_SMALLBUF if freq or mu is too small). */
+long lic_blob_tables(const void* blob, size_t len, int which, uint32_t* freq, size_t cap,
+                     float* mu, size_t mu_cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LIC_H */

@@ -1,0 +1,7 @@
+"""MI355X learned-image-codec library (HIP kernels + C++ pipeline runtime).
+
+Python side = argument marshalling over the C ABI of liblic.so
+(include/lic.h); every step of the codec runs in the library.
+"""
+from .codec import Codec, LicError, rans_decode, rans_encode, fnv1a  # noqa: F401
+from ._lib import LAYERS, LAYER_ID  # noqa: F401

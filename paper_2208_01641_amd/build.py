@@ -1,0 +1,59 @@
+"""Builds the HIP library liblic.so in-tree for gfx950.
+
+HIP sources go through hipcc (device code for gfx950 only, packed-FP32 ops
+disabled); the host-only runtime, entropy coder and C ABI are compiled by
+g++ (no FMA contraction, so the FP64 table construction is plain IEEE) and
+everything is linked by hipcc.
+"""
+import os
+import subprocess
+import sys
+from concurrent.futures import ThreadPoolExecutor
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "csrc")
+OUT = os.path.join(HERE, "_build")
+LIB = os.path.join(HERE, "liblic.so")
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+
+HIP_SOURCES = ["conv_kernels.hip"]
+CPP_SOURCES = ["entropy.cpp", "model.cpp", "pipeline.cpp", "api.cpp"]
+
+HIPCC = [os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+CXX = ["g++", "-O2", "-std=c++17", "-fPIC", "-ffp-contract=off", "-Wall", "-Wno-unused-function", "-Wno-unused-result",
+       "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include")]
+
+
+def _run(cmd):
+    p = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT, text=True)
+    out = "\n".join(l for l in p.stdout.splitlines() if "packed-fp32-ops" not in l)
+    if p.returncode != 0:
+        raise RuntimeError("build failed: %s\n%s" % (" ".join(cmd), out))
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    os.makedirs(OUT, exist_ok=True)
+    jobs = []
+    objs = []
+    for f in HIP_SOURCES:
+        o = os.path.join(OUT, f + ".o")
+        jobs.append(HIPCC + ["-c", os.path.join(SRC, f), "-o", o])
+        objs.append(o)
+    for f in CPP_SOURCES:
+        o = os.path.join(OUT, f + ".o")
+        jobs.append(CXX + ["-c", os.path.join(SRC, f), "-o", o])
+        objs.append(o)
+    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        for out in ex.map(_run, jobs):
+            if verbose and out.strip():
+                print(out)
+    tmp = LIB + ".tmp%d" % os.getpid()
+    _run(HIPCC + ["-shared", "-o", tmp] + objs + ["-lpthread"])
+    os.replace(tmp, LIB)
+    return LIB
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

@@ -1,0 +1,181 @@
+"""Python handle over the C ABI (marshalling only; torch supplies device memory)."""
+from __future__ import annotations
+
+import ctypes
+import json
+
+import numpy as np
+
+from . import _lib
+from ._lib import lib
+
+
+class LicError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{_lib.STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _ptr(a) -> int:
+    """Address of a torch tensor (host or device) or numpy array."""
+    if hasattr(a, "data_ptr"):
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def _is_device(a) -> int:
+    return int(hasattr(a, "is_cuda") and a.is_cuda)
+
+
+def _sync(*tensors):
+    if any(_is_device(t) for t in tensors if t is not None):
+        import torch
+        torch.cuda.synchronize()
+
+
+class Codec:
+    """A codec instance: packed weights, tables, pools and pipeline threads."""
+
+    def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1,
+                 y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 0, max_in_flight: int = 6,
+                 max_h: int = 1088, max_w: int = 1920, hbm_budget_bytes: int = 0, device: int = 0):
+        cfg = _lib.CodecConfig()
+        lib.codec_default_config(ctypes.byref(cfg))
+        cfg.kind, cfg.N, cfg.M, cfg.hs_out = kind, N, M, hs_out
+        cfg.y_slices, cfg.entropy_threads, cfg.zero_copy = y_slices, entropy_threads, zero_copy
+        cfg.max_in_flight, cfg.max_h, cfg.max_w = max_in_flight, max_h, max_w
+        cfg.hbm_budget_bytes, cfg.hip_device = hbm_budget_bytes, device
+        self.cfg = cfg
+        self.kind, self.N, self.M, self.S = kind, N, M, y_slices
+        self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
+        h = ctypes.c_void_p()
+        rc = lib.codec_create(ctypes.byref(cfg), self._blob, len(blob), ctypes.byref(h))
+        if rc != 0:
+            raise LicError(rc, lib.codec_last_error(None).decode())
+        self._h = h
+
+    # ------------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.codec_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def _check(self, rc):
+        if rc < 0:
+            raise LicError(rc, lib.codec_last_error(self._h).decode())
+        return rc
+
+    def max_stream_bytes(self, H: int, W: int) -> int:
+        Hp, Wp = 64 * -(-H // 64), 64 * -(-W // 64)
+        ny = (Hp // 16) * (Wp // 16) * self.M
+        nz = (Hp // 64) * (Wp // 64) * self.N if self.kind == 1 else 0
+        return 20 + 4 * (self.S + 1) + 2 * (ny + nz) + 16 * 65
+
+    # ------------------------------------------------------------------
+    def encode(self, x) -> list:
+        """x: [n, 3, H, W] float32 (torch tensor on the GPU or host, or numpy)."""
+        n, _, H, W = x.shape
+        cap = n * self.max_stream_bytes(H, W)
+        out = np.empty(cap, np.uint8)
+        lens = np.zeros(n, np.uint64)
+        _sync(x)
+        self._check(lib.codec_encode(self._h, _ptr(x), n, H, W, _is_device(x), out.ctypes.data, cap,
+                                     lens.ctypes.data))
+        res, off = [], 0
+        for ln in lens.tolist():
+            res.append(out[off:off + ln].tobytes())
+            off += ln
+        return res
+
+    def decode(self, streams, out):
+        """Decodes a list of bitstreams into out ([n, 3, H, W] float32, device or host)."""
+        n = len(streams)
+        buf = np.frombuffer(b"".join(streams), np.uint8).copy()
+        lens = np.array([len(s) for s in streams], np.uint64)
+        H, W = ctypes.c_int(), ctypes.c_int()
+        _sync(out)
+        self._check(lib.codec_decode(self._h, buf.ctypes.data, lens.ctypes.data, n, _ptr(out), out.numel()
+                                     if hasattr(out, "numel") else out.size, _is_device(out),
+                                     ctypes.byref(H), ctypes.byref(W)))
+        return H.value, W.value
+
+    def encode_decode(self, x, out) -> list:
+        """Encoder chained into the decoder, frame by frame; returns the bitstreams."""
+        n, _, H, W = x.shape
+        cap = n * self.max_stream_bytes(H, W)
+        bits = np.empty(cap, np.uint8)
+        lens = np.zeros(n, np.uint64)
+        _sync(x, out)
+        self._check(lib.codec_encode_decode(self._h, _ptr(x), n, H, W, _is_device(x), bits.ctypes.data, cap,
+                                            lens.ctypes.data, _ptr(out)))
+        res, off = [], 0
+        for ln in lens.tolist():
+            res.append(bits[off:off + ln].tobytes())
+            off += ln
+        return res
+
+    def run_layer(self, layer, n: int, H: int, W: int, inp, out, aux=None):
+        lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
+        _sync(inp, out, aux)
+        self._check(lib.codec_run_layer(self._h, lid, n, H, W, _ptr(inp), 0 if out is None else _ptr(out),
+                                        0 if aux is None else _ptr(aux)))
+
+    def latencies_ms(self) -> np.ndarray:
+        buf = np.zeros(1 << 16, np.float64)
+        n = self._check(lib.codec_last_latencies(self._h, buf.ctypes.data, buf.size))
+        return buf[:n].copy()
+
+    def stats(self) -> dict:
+        buf = ctypes.create_string_buffer(4096)
+        self._check(lib.codec_get_stats(self._h, buf, 4096))
+        return json.loads(buf.value.decode())
+
+    def tables(self, which: int) -> np.ndarray:
+        buf = np.zeros(512 * 129, np.uint32)
+        n = self._check(lib.codec_tables(self._h, which, buf.ctypes.data, buf.size))
+        return buf[:n].reshape(-1, 129).copy()
+
+    def medians(self) -> np.ndarray:
+        buf = np.zeros(512, np.float32)
+        n = self._check(lib.codec_medians(self._h, buf.ctypes.data, buf.size))
+        return buf[:n].copy()
+
+
+# ---------------------------------------------------------------- host coder
+def rans_encode(sym, tab, freq) -> bytes:
+    sym = np.ascontiguousarray(sym, np.uint8).ravel()
+    tab = np.ascontiguousarray(tab, np.uint8).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    cap = 2 * sym.size + 64
+    out = np.empty(cap, np.uint8)
+    n = lib.lic_rans_encode(sym.ctypes.data, tab.ctypes.data, sym.size, freq.ctypes.data, freq.shape[0],
+                            out.ctypes.data, cap)
+    if n < 0:
+        raise LicError(n, "lic_rans_encode")
+    return out[:n].tobytes()
+
+
+def rans_decode(data: bytes, tab, freq, n: int) -> np.ndarray:
+    tab = np.ascontiguousarray(tab, np.uint8).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    buf = np.frombuffer(data, np.uint8).copy() if data else np.zeros(1, np.uint8)
+    sym = np.empty(n, np.uint8)
+    rc = lib.lic_rans_decode(buf.ctypes.data, len(data), tab.ctypes.data, n, freq.ctypes.data, freq.shape[0],
+                             sym.ctypes.data)
+    if rc != 0:
+        raise LicError(rc, "lic_rans_decode")
+    return sym
+
+
+def fnv1a(data: bytes) -> int:
+    buf = np.frombuffer(data, np.uint8).copy() if data else np.zeros(1, np.uint8)
+    return int(lib.lic_fnv1a(buf.ctypes.data, len(data)))

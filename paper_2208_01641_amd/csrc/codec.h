@@ -1,0 +1,256 @@
+// Internal codec object: model (packed weights, tables), device pools and
+// the pipeline runtime behind the C ABI.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include <atomic>
+#include <condition_variable>
+#include <deque>
+#include <functional>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/lic.h"
+#include "conv_args.h"
+#include "entropy.h"
+#include "kernels.h"
+
+namespace lic {
+
+// ------------------------------------------------------------------ model
+struct LayerGPU {
+    bool present = false;
+    int ld = 0, ep = 0;
+    int cin = 0, co = 0, cop = 0;
+    int k = 5;
+    bool deconv = false;
+    bool rows = false;                 // 4 phases as GEMM rows (transposed conv to 3 channels)
+    int nphase = 1;
+    std::vector<PhaseDesc> host_ph;
+    PhaseDesc* d_ph = nullptr;
+    float* d_w = nullptr;
+    float* d_bias = nullptr;
+    float* d_gamma = nullptr;
+    float* d_beta = nullptr;
+    const float* d_qmu = nullptr;      // EP_QUANT offsets
+    const float* d_mu_in = nullptr;    // LD_I8 offsets
+};
+
+struct Geo {
+    int Hin, Win, Hg, Wg, s_in, Hout, Wout, s_out;
+};
+
+// Tensor sizes for an H x W frame (padded to multiples of 64).
+struct FrameDims {
+    int H, W, Hp, Wp, Hy, Wy, Hz, Wz;
+    explicit FrameDims(int h = 0, int w = 0)
+        : H(h), W(w), Hp(64 * ((h + 63) / 64)), Wp(64 * ((w + 63) / 64)),
+          Hy(Hp / 16), Wy(Wp / 16), Hz(Hp / 64), Wz(Wp / 64) {}
+};
+
+// ------------------------------------------------------------- pipeline
+struct Codec;
+
+constexpr int kMaxSlices = 64;
+
+// Per-frame task: the state machine that travels through the stage queues.
+struct Task {
+    int frame = 0;
+    int slot = -1;
+    int stage = 0;                     // index into the pipeline's stage list
+    const float* x = nullptr;          // input frame (caller memory)
+    float* xhat = nullptr;             // output frame (caller memory)
+    const uint8_t* bits_in = nullptr;  // decode input
+    size_t bits_in_len = 0;
+    std::atomic<int> jobs_left{0};
+    int status = 0;
+    std::string err;
+    double t_admit = 0.0, t_done = 0.0;
+    size_t bits_len = 0;               // encoded length (in the slot buffer)
+    // encoder: lengths of the z stream (part 0 for the hyperprior) and y slices
+    size_t part_len[kMaxSlices + 1] = {};
+    // decoder: payload spans of the parsed bitstream
+    const uint8_t* zp = nullptr;
+    size_t zlen = 0;
+    const uint8_t* yp[kMaxSlices] = {};
+    size_t ylen[kMaxSlices] = {};
+};
+
+// Pooled per-frame buffers.  Host buffers are pinned (and mapped into the
+// device address space for zero-copy stores from the epilogues).
+struct Slot {
+    int8_t* h_sym_y = nullptr;   int8_t* d_sym_y = nullptr;    // [Hy][Wy][M]
+    int8_t* h_sym_z = nullptr;   int8_t* d_sym_z = nullptr;    // [Hz][Wz][N]
+    uint8_t* h_idx = nullptr;    uint8_t* d_idx = nullptr;     // [Hy][Wy][M]
+    int8_t* dm_sym_y = nullptr;  int8_t* dm_sym_z = nullptr;   // device views of the pinned buffers
+    uint8_t* dm_idx = nullptr;
+    uint8_t* h_scratch = nullptr; size_t scratch_cap = 0;     // per-slice rANS output regions
+    uint8_t* h_bits = nullptr;    size_t bits_cap = 0;         // assembled bitstream
+    float* d_x = nullptr;                                      // input staging (host input)
+    float* d_xhat = nullptr;                                   // output staging (host output)
+};
+
+// Device scratch of one GPU stage (reused frame after frame in stream order).
+struct StageScratch {
+    float* a = nullptr;   // N x Hp/2 x Wp/2
+    float* b = nullptr;   // N x Hp/4 x Wp/4
+    float* y = nullptr;   // M x Hy x Wy
+    float* h1 = nullptr;  // N x Hy x Wy
+    float* h2 = nullptr;  // N x Hy/2 x Wy/2 (and h_s middle: N x Hy/2 x Wy/2)
+};
+
+enum StageKind { ST_GPU_ENC, ST_CPU_ENC, ST_CPU_DEC_Z, ST_GPU_HS, ST_CPU_DEC_Y, ST_GPU_GS };
+
+struct Job {
+    Task* task;
+    int part;
+};
+
+template <class T>
+class BlockingQueue {
+public:
+    void push(T v)
+    {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            q_.push_back(std::move(v));
+        }
+        cv_.notify_one();
+    }
+    // false once closed and drained
+    bool pop(T* out)
+    {
+        std::unique_lock<std::mutex> g(m_);
+        cv_.wait(g, [&] { return closed_ || !q_.empty(); });
+        if (q_.empty()) return false;
+        *out = std::move(q_.front());
+        q_.pop_front();
+        return true;
+    }
+    bool try_pop(T* out)
+    {
+        std::lock_guard<std::mutex> g(m_);
+        if (q_.empty()) return false;
+        *out = std::move(q_.front());
+        q_.pop_front();
+        return true;
+    }
+    bool empty()
+    {
+        std::lock_guard<std::mutex> g(m_);
+        return q_.empty();
+    }
+    void close()
+    {
+        {
+            std::lock_guard<std::mutex> g(m_);
+            closed_ = true;
+        }
+        cv_.notify_all();
+    }
+
+private:
+    std::mutex m_;
+    std::condition_variable cv_;
+    std::deque<T> q_;
+    bool closed_ = false;
+};
+
+struct CallState {
+    int n = 0;
+    int S = 1;                     // y slices of every frame in the call
+    FrameDims dims;
+    int is_device = 0;
+    std::vector<StageKind> stages;
+    std::vector<std::unique_ptr<Task>> tasks;
+    // in-order sink
+    std::mutex m;
+    std::condition_variable cv;
+    int next_sink = 0;
+    int done = 0;
+    std::vector<char> finished;
+    uint8_t* out = nullptr;        // encoded output (packed back to back)
+    size_t cap = 0;
+    size_t* lens = nullptr;
+    size_t offset = 0;
+    bool overflow = false;
+    int status = 0;
+    std::string err;
+};
+
+struct GpuStage {
+    StageKind kind;
+    hipStream_t stream = nullptr;
+    StageScratch scratch;
+    BlockingQueue<Task*> queue;
+    std::thread thread;
+    double busy_s = 0.0;
+};
+
+struct Codec {
+    codec_config cfg{};
+    std::string err;
+    int kind = 1, N = 128, M = 192, hs_exp = 1, S = 8;
+    uint32_t model_id = 0;
+    std::vector<float> medians;        // channel offsets of the factorized tables
+    TableSet fact;                     // [C] factorized tables
+    TableSet gauss;                    // [64] Gaussian tables
+    std::vector<float> thr;            // 63 scale-index thresholds
+    LayerGPU layers[LIC_NUM_LAYERS];
+    float* d_medians = nullptr;
+    float* d_zero = nullptr;
+    float* d_thr = nullptr;
+    std::vector<void*> dev_allocs, host_allocs;
+    size_t dev_bytes = 0;
+    std::atomic<long> alloc_events{0};
+
+    // runtime
+    hipStream_t layer_stream = nullptr;      // codec_run_layer
+    GpuStage gpu[3];                         // encoder GPU, decoder GPU1 (h_s), decoder GPU2 (g_s)
+    std::vector<Slot> slots;
+    BlockingQueue<int> free_slots;
+    BlockingQueue<Job> jobs;
+    std::vector<std::thread> workers;
+    CallState* call = nullptr;
+    std::vector<double> last_lat_ms;
+    double last_wall_s = 0.0;
+    int last_frames = 0;
+    std::atomic<long> cpu_busy_us{0};
+    bool started = false;
+
+    ~Codec();
+    // model
+    int load(const void* blob, size_t len);
+    int build_layers(const std::map<std::string, std::pair<std::vector<int>, std::vector<double>>>& P);
+    Geo geo(int layer, const FrameDims& d) const;
+    int launch_layer(int layer, int n, const FrameDims& d, const void* in, void* out, void* aux,
+                     hipStream_t s, std::string* errp);
+    // pools and threads
+    int start();
+    void stop();
+    // pipeline
+    int run_call(CallState& cs);
+    void gpu_loop(int g);
+    void worker_loop();
+    void advance(Task* t);
+    void finish_task(Task* t);
+    int gpu_encode(Task* t, GpuStage& g);
+    int gpu_hs(Task* t, GpuStage& g);
+    int gpu_gs(Task* t, GpuStage& g);
+    int cpu_job(Task* t, int part);
+    int cpu_parts(StageKind k) const;
+    int cpu_finalize(Task* t, StageKind k);
+    // allocation helpers (create time only)
+    void* dev_alloc(size_t bytes);
+    void* host_alloc(size_t bytes);
+};
+
+double now_s();
+// Host-only: entropy tables a codec would build from a blob (no GPU needed).
+long blob_tables(const void* blob, size_t len, int which, uint32_t* freq, size_t cap, float* mu, size_t mu_cap);
+
+}  // namespace lic

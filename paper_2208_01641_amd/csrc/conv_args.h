@@ -1,0 +1,58 @@
+// Launch descriptors shared by the host-side planner and the HIP kernels.
+#pragma once
+#include <stdint.h>
+
+namespace lic {
+
+// Input loaders (what the implicit-GEMM "pixel" operand is read from).
+enum Loader : int {
+    LD_F32 = 0,      // float NHWC activations
+    LD_F32_ABS = 1,  // |float| NHWC (h_a takes |y|)
+    LD_I8 = 2,       // int8 NHWC symbols, dequantised as sym + mu[c]
+    LD_RGB = 3,      // float NCHW 3-channel image, unpadded (ingest + zero pad)
+};
+
+// Epilogues fused after the K loop.
+enum Epilogue : int {
+    EP_NONE = 0,
+    EP_RELU = 1,
+    EP_GDN = 2,      // y = x / sqrt(beta + gamma (x*x))   (all channels in one wave)
+    EP_IGDN = 3,     // y = x * sqrt(beta + gamma (x*x))
+    EP_QUANT = 4,    // out = v (float), aux = clamp(rne(v - mu[c]), -64, 64) int8
+    EP_INDEX = 5,    // out = scale-table index uint8, aux = v (float, optional)
+    EP_RGB = 6,      // transposed conv to 3 channels, 4 phases as 12 GEMM rows:
+                     // out = clamp(v, 0, 1) cropped NCHW, aux = v padded NCHW
+};
+
+// One phase of a layer.  A plain convolution has one phase; a stride-2
+// transposed convolution is split into the four sub-pixel phases, each a
+// stride-1 convolution over the input grid with its own subset of taps.
+struct PhaseDesc {
+    int32_t ntaps;
+    int32_t oy, ox;          // output position = s_out * grid + (oy, ox)
+    int32_t pad_;
+    const float* w;          // packed weights [ntaps][CoP][CIN] (device)
+    int8_t dy[32], dx[32];   // tap offsets: input = s_in * grid + (dy, dx)
+};
+
+struct ConvArgs {
+    const void* in;
+    void* out;
+    void* aux;
+    const PhaseDesc* ph;     // [nphase] (device)
+    const float* bias;       // [CoP]
+    const float* mu_in;      // LD_I8 offsets [CIN]
+    const float* gamma;      // GDN [Co][Co]
+    const float* beta;       // GDN [Co]
+    const float* qmu;        // EP_QUANT offsets [Co]
+    const float* thr;        // EP_INDEX thresholds [63]
+    int n, Hin, Win;         // input tensor (per image)
+    int Hg, Wg, s_in;        // GEMM pixel grid (per image)
+    int Hout, Wout, s_out;   // output tensor (per image)
+    int Co;                  // real output channels
+    int nphase, ncog;        // phases, output-channel groups
+    int hs_exp;              // EP_INDEX: 1 = thresholds are ln(t_k), else t_k with ReLU
+    int Hc, Wc;              // EP_RGB crop size
+};
+
+}  // namespace lic

@@ -1,0 +1,305 @@
+// Entropy model and byte-wise rANS coder (host).
+//
+// The CPU half of the codec (Section III.A-B): integer frequency tables of
+// the factorized prior (per channel) and of the Gaussian conditional (per
+// scale-table entry), and the entropy coder that turns symbols into the
+// per-frame strings.  Byte-wise rANS with a 32-bit state follows the
+// published construction (Duda 2013; Giesen 2014): the state lives in
+// [2^23, 2^31); before coding a symbol of frequency f the encoder emits
+// low bytes while the state is at least 2^15 f, then maps x to
+// floor(x / f) 2^16 + x mod f + start.  Streams carry their final state in
+// front so that the decoder reads forward.
+#include "entropy.h"
+
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+namespace lic {
+
+// --------------------------------------------------------------- density
+static inline double softplus(double v) { return log1p(exp(v)); }
+
+double density_logit(const double* prm, double x)
+{
+    // layer widths 1 -> 3 -> 3 -> 3 -> 1; per layer: matrix (out x in, raw),
+    // bias (out), and for the three hidden layers a factor vector (out)
+    const int width[5] = {1, 3, 3, 3, 1};
+    double cur[3] = {x, 0.0, 0.0};
+    int off = 0;
+    for (int layer = 0; layer < 4; ++layer) {
+        const int nin = width[layer], nout = width[layer + 1];
+        const double* mat = prm + off;
+        const double* bias = mat + nin * nout;
+        const double* fac = bias + nout;
+        off += nin * nout + nout + (layer < 3 ? nout : 0);
+        double nxt[3];
+        for (int o = 0; o < nout; ++o) {
+            double u = bias[o];
+            for (int i = 0; i < nin; ++i) u += softplus(mat[o * nin + i]) * cur[i];
+            if (layer < 3) u = u + tanh(fac[o]) * tanh(u);
+            nxt[o] = u;
+        }
+        for (int o = 0; o < nout; ++o) cur[o] = nxt[o];
+    }
+    return cur[0];
+}
+
+static inline double density_cdf(const double* prm, double x)
+{
+    return 1.0 / (1.0 + exp(-density_logit(prm, x)));
+}
+
+double density_median(const double* prm)
+{
+    double a = -64.0, b = 64.0;
+    for (int step = 0; step < 60; ++step) {
+        const double m = 0.5 * (a + b);
+        if (density_logit(prm, m) < 0.0) a = m; else b = m;
+    }
+    return 0.5 * (a + b);
+}
+
+void pmf_factorized(const double* prm, double mu, double* p)
+{
+    for (int s = 0; s < kNumSym; ++s) {
+        const int v = s + kSymMin;
+        const double upper = (v == 64) ? 1.0 : density_cdf(prm, v + 0.5 + mu);
+        const double lower = (v == -64) ? 0.0 : density_cdf(prm, v - 0.5 + mu);
+        p[s] = upper - lower;
+    }
+}
+
+static inline double phi(double u) { return 0.5 * erfc(-u / sqrt(2.0)); }
+
+void pmf_gaussian(double t, double* p)
+{
+    for (int s = 0; s < kNumSym; ++s) {
+        const int v = s + kSymMin;
+        p[s] = (v == -64 || v == 64) ? phi(-63.5 / t) : phi((v + 0.5) / t) - phi((v - 0.5) / t);
+    }
+}
+
+void quantize_pmf(const double* p, uint32_t* f)
+{
+    const double total = (double)(1u << kPrecBits);
+    uint32_t used = 0;
+    int mode = 0;
+    for (int s = 0; s < kNumSym; ++s) {
+        f[s] = 1u + (uint32_t)floor(p[s] * (total - kNumSym));
+        used += f[s];
+        if (p[s] > p[mode]) mode = s;
+    }
+    f[mode] += (1u << kPrecBits) - used;
+}
+
+void scale_table(double* t)
+{
+    const double a = log(0.11), b = log(256.0);
+    for (int k = 0; k < kScales; ++k) t[k] = exp(a + k * (b - a) / 63.0);
+    t[0] = 0.11;
+    t[kScales - 1] = 256.0;
+}
+
+// ----------------------------------------------------------------- tables
+void TableSet::init(int n, const uint32_t* f, bool with_lut)
+{
+    ntab = n;
+    freq.assign(f, f + (size_t)n * kNumSym);
+    start.assign((size_t)n * (kNumSym + 1), 0);
+    for (int t = 0; t < n; ++t) {
+        uint32_t s = 0;
+        for (int a = 0; a < kNumSym; ++a) {
+            start[(size_t)t * (kNumSym + 1) + a] = s;
+            s += freq[(size_t)t * kNumSym + a];
+        }
+        start[(size_t)t * (kNumSym + 1) + kNumSym] = s;
+    }
+    lut.clear();
+    if (with_lut) {
+        lut.resize((size_t)n << kPrecBits);
+        for (int t = 0; t < n; ++t) {
+            uint8_t* L = lut.data() + ((size_t)t << kPrecBits);
+            const uint32_t* st = start.data() + (size_t)t * (kNumSym + 1);
+            for (int a = 0; a < kNumSym; ++a)
+                memset(L + st[a], a, st[a + 1] - st[a]);
+        }
+    }
+}
+
+// ------------------------------------------------------------------- rANS
+namespace {
+
+struct Writer {
+    uint8_t* base;
+    long pos;     // bytes are written at decreasing positions
+    bool ok = true;
+};
+
+inline void enc_put(uint32_t& x, uint32_t f, uint32_t st, Writer& w)
+{
+    const uint32_t limit = ((kRansLow >> kPrecBits) << 8) * f;   // 2^15 f
+    while (x >= limit) {
+        if (w.pos == 0) { w.ok = false; return; }
+        w.base[--w.pos] = (uint8_t)x;
+        x >>= 8;
+    }
+    x = ((x / f) << kPrecBits) + (x % f) + st;
+}
+
+inline long enc_finish(uint32_t x, Writer& w, size_t cap)
+{
+    if (!w.ok || w.pos < 4) return -1;
+    w.pos -= 4;
+    w.base[w.pos + 0] = (uint8_t)x;
+    w.base[w.pos + 1] = (uint8_t)(x >> 8);
+    w.base[w.pos + 2] = (uint8_t)(x >> 16);
+    w.base[w.pos + 3] = (uint8_t)(x >> 24);
+    const long len = (long)cap - w.pos;
+    memmove(w.base, w.base + w.pos, (size_t)len);
+    return len;
+}
+
+inline int find_symbol(const TableSet& T, int t, uint32_t slot)
+{
+    if (!T.lut.empty()) return T.lut[((size_t)t << kPrecBits) + slot];
+    const uint32_t* st = T.start.data() + (size_t)t * (kNumSym + 1);
+    // largest a with st[a] <= slot
+    int lo = 0, hi = kNumSym - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (st[mid] <= slot) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <class TabOf>
+long encode_impl(const int8_t* sym, long n, const TableSet& T, uint8_t* out, size_t cap, TabOf tab_of)
+{
+    Writer w{out, (long)cap};
+    uint32_t x = kRansLow;
+    for (long i = n - 1; i >= 0; --i) {
+        const int t = tab_of(i);
+        const int a = (int)sym[i] - kSymMin;
+        enc_put(x, T.freq[(size_t)t * kNumSym + a], T.start[(size_t)t * (kNumSym + 1) + a], w);
+        if (!w.ok) return -1;
+    }
+    return enc_finish(x, w, cap);
+}
+
+template <class TabOf>
+int decode_impl(const uint8_t* in, size_t len, long n, const TableSet& T, int8_t* sym, TabOf tab_of)
+{
+    if (len < 4) return -1;
+    uint32_t x = (uint32_t)in[0] | ((uint32_t)in[1] << 8) | ((uint32_t)in[2] << 16) | ((uint32_t)in[3] << 24);
+    size_t pos = 4;
+    const uint32_t mask = (1u << kPrecBits) - 1;
+    for (long i = 0; i < n; ++i) {
+        const int t = tab_of(i);
+        const uint32_t slot = x & mask;
+        const int a = find_symbol(T, t, slot);
+        sym[i] = (int8_t)(a + kSymMin);
+        x = T.freq[(size_t)t * kNumSym + a] * (x >> kPrecBits) + slot - T.start[(size_t)t * (kNumSym + 1) + a];
+        while (x < kRansLow) {
+            if (pos >= len) return -1;
+            x = (x << 8) | in[pos++];
+        }
+    }
+    return (x == kRansLow && pos == len) ? 0 : -1;
+}
+
+}  // namespace
+
+long rans_encode(const int8_t* sym, const uint8_t* tab, long n, const TableSet& T, uint8_t* out, size_t cap)
+{
+    return encode_impl(sym, n, T, out, cap, [tab](long i) { return (int)tab[i]; });
+}
+
+long rans_encode_channel(const int8_t* sym, long n, int C, const TableSet& T, uint8_t* out, size_t cap)
+{
+    return encode_impl(sym, n, T, out, cap, [C](long i) { return (int)(i % C); });
+}
+
+int rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n, const TableSet& T, int8_t* sym)
+{
+    return decode_impl(in, len, n, T, sym, [tab](long i) { return (int)tab[i]; });
+}
+
+int rans_decode_channel(const uint8_t* in, size_t len, long n, int C, const TableSet& T, int8_t* sym)
+{
+    return decode_impl(in, len, n, T, sym, [C](long i) { return (int)(i % C); });
+}
+
+uint32_t fnv1a(const void* data, size_t len)
+{
+    const uint8_t* p = static_cast<const uint8_t*>(data);
+    uint32_t h = 2166136261u;
+    for (size_t i = 0; i < len; ++i) {
+        h ^= p[i];
+        h *= 16777619u;
+    }
+    return h;
+}
+
+// -------------------------------------------------------------- container
+static inline void put16(uint8_t* p, uint32_t v) { p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); }
+static inline void put32(uint8_t* p, uint32_t v)
+{
+    p[0] = (uint8_t)v; p[1] = (uint8_t)(v >> 8); p[2] = (uint8_t)(v >> 16); p[3] = (uint8_t)(v >> 24);
+}
+static inline uint32_t get16(const uint8_t* p) { return (uint32_t)p[0] | ((uint32_t)p[1] << 8); }
+static inline uint32_t get32(const uint8_t* p)
+{
+    return (uint32_t)p[0] | ((uint32_t)p[1] << 8) | ((uint32_t)p[2] << 16) | ((uint32_t)p[3] << 24);
+}
+
+void write_header(uint8_t* out, const StreamHeader& h, uint32_t len_z, const uint32_t* len_y)
+{
+    memcpy(out, "LICS", 4);
+    out[4] = 1;
+    out[5] = (uint8_t)h.kind;
+    out[6] = (uint8_t)(h.hs_exp & 1);
+    out[7] = (uint8_t)h.S;
+    put16(out + 8, h.H);
+    put16(out + 10, h.W);
+    put16(out + 12, h.N);
+    put16(out + 14, h.M);
+    put32(out + 16, h.model_id);
+    uint8_t* p = out + kHeaderBytes;
+    if (h.kind == 1) { put32(p, len_z); p += 4; }
+    for (int s = 0; s < h.S; ++s, p += 4) put32(p, len_y[s]);
+}
+
+bool parse_stream(const uint8_t* bits, size_t len, StreamHeader* h, const uint8_t** z, size_t* len_z,
+                  std::vector<const uint8_t*>* y, std::vector<size_t>* len_y, std::string* err)
+{
+    if (len < kHeaderBytes || memcmp(bits, "LICS", 4) != 0) { *err = "not a LICS bitstream"; return false; }
+    if (bits[4] != 1) { *err = "unsupported bitstream version"; return false; }
+    h->kind = bits[5];
+    h->hs_exp = bits[6] & 1;
+    h->S = bits[7];
+    h->H = (int)get16(bits + 8);
+    h->W = (int)get16(bits + 10);
+    h->N = (int)get16(bits + 12);
+    h->M = (int)get16(bits + 14);
+    h->model_id = get32(bits + 16);
+    if ((h->kind != 0 && h->kind != 1) || h->S < 1 || h->H < 1 || h->W < 1) { *err = "bad header"; return false; }
+    const size_t hs = header_size(h->kind, h->S);
+    if (len < hs) { *err = "truncated header"; return false; }
+    const uint8_t* p = bits + kHeaderBytes;
+    size_t pos = hs;
+    *z = nullptr;
+    *len_z = 0;
+    if (h->kind == 1) { *len_z = get32(p); p += 4; }
+    len_y->resize(h->S);
+    y->resize(h->S);
+    size_t total = *len_z;
+    for (int s = 0; s < h->S; ++s, p += 4) { (*len_y)[s] = get32(p); total += (*len_y)[s]; }
+    if (total != len - hs) { *err = "payload length mismatch"; return false; }
+    if (h->kind == 1) { *z = bits + pos; pos += *len_z; }
+    for (int s = 0; s < h->S; ++s) { (*y)[s] = bits + pos; pos += (*len_y)[s]; }
+    return true;
+}
+
+}  // namespace lic

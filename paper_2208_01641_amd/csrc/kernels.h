@@ -1,0 +1,23 @@
+// Host-side interface to the HIP kernels.
+#pragma once
+#include <hip/hip_runtime_api.h>
+
+#include "conv_args.h"
+
+namespace lic {
+
+// Template configuration of one implicit-GEMM kernel instantiation:
+// input channels per tap (K chunking), m-tiles (16 output channels each) and
+// n-tiles (16 pixels each) per wave, waves per block, loader and epilogue.
+struct KernelKey {
+    int cin, mt, nt, waves, ld, ep;
+    bool operator==(const KernelKey& o) const
+    {
+        return cin == o.cin && mt == o.mt && nt == o.nt && waves == o.waves && ld == o.ld && ep == o.ep;
+    }
+};
+
+bool kernel_available(const KernelKey& k);
+hipError_t launch_conv(const KernelKey& k, const ConvArgs& args, int nblocks, hipStream_t stream);
+
+}  // namespace lic

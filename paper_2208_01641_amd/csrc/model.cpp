@@ -1,0 +1,465 @@
+// Model loading: weight blob parsing, entropy tables, weight packing for the
+// implicit-GEMM kernels, per-layer geometry and launch planning.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+
+#include "codec.h"
+
+namespace lic {
+
+#define HIP_TRY(expr)                                                              \
+    do {                                                                           \
+        hipError_t e_ = (expr);                                                    \
+        if (e_ != hipSuccess) {                                                    \
+            err = std::string(#expr) + ": " + hipGetErrorString(e_);               \
+            return LIC_E_HIP;                                                      \
+        }                                                                          \
+    } while (0)
+
+void* Codec::dev_alloc(size_t bytes)
+{
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes ? bytes : 16) != hipSuccess) return nullptr;
+    dev_allocs.push_back(p);
+    dev_bytes += bytes;
+    alloc_events++;
+    return p;
+}
+
+void* Codec::host_alloc(size_t bytes)
+{
+    void* p = nullptr;
+    if (hipHostMalloc(&p, bytes ? bytes : 16, hipHostMallocMapped) != hipSuccess) return nullptr;
+    host_allocs.push_back(p);
+    alloc_events++;
+    return p;
+}
+
+namespace {
+
+using ParamMap = std::map<std::string, std::pair<std::vector<int>, std::vector<double>>>;
+
+bool parse_blob(const uint8_t* b, size_t len, int* kind, int* N, int* M, ParamMap* P, std::string* err)
+{
+    auto rd32 = [&](size_t pos) {
+        uint32_t v;
+        memcpy(&v, b + pos, 4);
+        return v;
+    };
+    if (len < 24 || memcmp(b, "LICW", 4) != 0) { *err = "weight blob: bad magic"; return false; }
+    if (rd32(4) != 1) { *err = "weight blob: unsupported version"; return false; }
+    *kind = (int)rd32(8);
+    *N = (int)rd32(12);
+    *M = (int)rd32(16);
+    const uint32_t count = rd32(20);
+    size_t pos = 24;
+    for (uint32_t e = 0; e < count; ++e) {
+        if (pos + 2 > len) { *err = "weight blob: truncated"; return false; }
+        uint16_t nl;
+        memcpy(&nl, b + pos, 2);
+        pos += 2;
+        if (pos + nl + 2 > len) { *err = "weight blob: truncated"; return false; }
+        std::string name((const char*)b + pos, nl);
+        pos += nl;
+        const int code = b[pos], ndim = b[pos + 1];
+        pos += 2;
+        if ((code != 0 && code != 1) || ndim > 4 || pos + 4u * ndim > len) { *err = "weight blob: bad entry"; return false; }
+        std::vector<int> dims(ndim);
+        size_t count_el = 1;
+        for (int d = 0; d < ndim; ++d) {
+            dims[d] = (int)rd32(pos);
+            pos += 4;
+            count_el *= (size_t)dims[d];
+        }
+        const size_t esz = code == 0 ? 4 : 8;
+        if (pos + count_el * esz > len) { *err = "weight blob: truncated data"; return false; }
+        std::vector<double> vals(count_el);
+        for (size_t i = 0; i < count_el; ++i) {
+            if (code == 0) {
+                float f;
+                memcpy(&f, b + pos + 4 * i, 4);
+                vals[i] = f;
+            } else {
+                memcpy(&vals[i], b + pos + 8 * i, 8);
+            }
+        }
+        pos += count_el * esz;
+        (*P)[name] = {dims, std::move(vals)};
+    }
+    return true;
+}
+
+}  // namespace
+
+bool build_tables(const ParamMap& P, int kind, int N, int M, std::vector<float>* medians,
+                  std::vector<uint32_t>* fact_freq, std::vector<uint32_t>* gauss_freq, std::string* err)
+{
+    auto it = P.find("eb.density");
+    const int C = kind == 0 ? M : N;
+    if (it == P.end() || it->second.second.size() != (size_t)C * kDensityParams) {
+        *err = "weight blob: eb.density missing or of the wrong size";
+        return false;
+    }
+    const std::vector<double>& dens = it->second.second;
+    medians->resize(C);
+    fact_freq->assign((size_t)C * kNumSym, 0);
+    std::vector<double> pmf(kNumSym);
+    for (int c = 0; c < C; ++c) {
+        const double* prm = dens.data() + (size_t)c * kDensityParams;
+        (*medians)[c] = (float)density_median(prm);
+        pmf_factorized(prm, (double)(*medians)[c], pmf.data());
+        quantize_pmf(pmf.data(), fact_freq->data() + (size_t)c * kNumSym);
+    }
+    gauss_freq->clear();
+    if (kind == 1) {
+        double t[kScales];
+        scale_table(t);
+        gauss_freq->assign((size_t)kScales * kNumSym, 0);
+        for (int k = 0; k < kScales; ++k) {
+            pmf_gaussian(t[k], pmf.data());
+            quantize_pmf(pmf.data(), gauss_freq->data() + (size_t)k * kNumSym);
+        }
+    }
+    return true;
+}
+
+int Codec::load(const void* blob, size_t len)
+{
+    ParamMap P;
+    int bk, bn, bm;
+    if (!parse_blob(static_cast<const uint8_t*>(blob), len, &bk, &bn, &bm, &P, &err)) return LIC_E_ARG;
+    if (bk != cfg.kind || bn != cfg.N || bm != cfg.M) {
+        err = "weight blob kind/N/M does not match the configuration";
+        return LIC_E_MODEL;
+    }
+    kind = cfg.kind;
+    N = cfg.N;
+    M = cfg.M;
+    hs_exp = cfg.hs_out == LIC_HS_EXP ? 1 : 0;
+    S = cfg.y_slices;
+    model_id = fnv1a(blob, len);
+
+    // entropy model: per-channel medians, factorized and Gaussian tables
+    std::vector<uint32_t> ff, gf;
+    if (!build_tables(P, kind, N, M, &medians, &ff, &gf, &err)) return LIC_E_MODEL;
+    fact.init(kind == 0 ? M : N, ff.data(), kind == 0);
+    if (kind == 1) {
+        gauss.init(kScales, gf.data(), true);
+        double t[kScales];
+        scale_table(t);
+        thr.resize(63);
+        for (int k = 0; k < 63; ++k) thr[k] = hs_exp ? (float)log(t[k]) : (float)t[k];
+    }
+    return build_layers(P);
+}
+
+long blob_tables(const void* blob, size_t len, int which, uint32_t* freq, size_t cap, float* mu, size_t mu_cap)
+{
+    ParamMap P;
+    int kind, N, M;
+    std::string e;
+    if (!parse_blob(static_cast<const uint8_t*>(blob), len, &kind, &N, &M, &P, &e)) return LIC_E_ARG;
+    std::vector<float> med;
+    std::vector<uint32_t> ff, gf;
+    if (!build_tables(P, kind, N, M, &med, &ff, &gf, &e)) return LIC_E_MODEL;
+    const std::vector<uint32_t>& src = which == 0 ? ff : gf;
+    if (which != 0 && which != 1) return LIC_E_ARG;
+    if (src.size() > cap || (mu && med.size() > mu_cap)) return LIC_E_SMALLBUF;
+    std::copy(src.begin(), src.end(), freq);
+    if (mu) std::copy(med.begin(), med.end(), mu);
+    return (long)src.size();
+}
+
+namespace {
+
+struct Spec {
+    int id;
+    const char* name;
+    int ld, ep;
+    bool deconv;
+    int k;
+};
+
+}  // namespace
+
+int Codec::build_layers(const ParamMap& P)
+{
+    HIP_TRY(hipSetDevice(cfg.hip_device));
+    const int C = kind == 0 ? M : N;
+    d_medians = (float*)dev_alloc(sizeof(float) * 512);
+    d_zero = (float*)dev_alloc(sizeof(float) * 512);
+    d_thr = (float*)dev_alloc(sizeof(float) * 64);
+    if (!d_medians || !d_zero || !d_thr) { err = "device allocation failed"; return LIC_E_NOMEM; }
+    std::vector<float> tmp(512, 0.0f);
+    HIP_TRY(hipMemcpy(d_zero, tmp.data(), 512 * sizeof(float), hipMemcpyHostToDevice));
+    std::copy(medians.begin(), medians.end(), tmp.begin());
+    HIP_TRY(hipMemcpy(d_medians, tmp.data(), 512 * sizeof(float), hipMemcpyHostToDevice));
+    if (!thr.empty()) HIP_TRY(hipMemcpy(d_thr, thr.data(), 63 * sizeof(float), hipMemcpyHostToDevice));
+    (void)C;
+
+    std::vector<Spec> specs = {
+        {LIC_GA0, "ga0", LD_RGB, EP_GDN, false, 5}, {LIC_GA1, "ga1", LD_F32, EP_GDN, false, 5},
+        {LIC_GA2, "ga2", LD_F32, EP_GDN, false, 5}, {LIC_GA3, "ga3", LD_F32, EP_QUANT, false, 5},
+        {LIC_GS0, "gs0", LD_I8, EP_IGDN, true, 5},  {LIC_GS1, "gs1", LD_F32, EP_IGDN, true, 5},
+        {LIC_GS2, "gs2", LD_F32, EP_IGDN, true, 5}, {LIC_GS3, "gs3", LD_F32, EP_RGB, true, 5},
+    };
+    if (kind == 1) {
+        std::vector<Spec> hyper = {
+            {LIC_HA0, "ha0", LD_F32_ABS, EP_RELU, false, 3}, {LIC_HA1, "ha1", LD_F32, EP_RELU, false, 5},
+            {LIC_HA2, "ha2", LD_F32, EP_QUANT, false, 5},    {LIC_HS0, "hs0", LD_I8, EP_RELU, true, 5},
+            {LIC_HS1, "hs1", LD_F32, EP_RELU, true, 5},      {LIC_HS2, "hs2", LD_F32, EP_INDEX, false, 3},
+        };
+        specs.insert(specs.end(), hyper.begin(), hyper.end());
+    }
+
+    for (const Spec& sp : specs) {
+        LayerGPU& L = layers[sp.id];
+        auto wit = P.find(std::string(sp.name) + ".w");
+        auto bit = P.find(std::string(sp.name) + ".b");
+        if (wit == P.end() || bit == P.end() || wit->second.first.size() != 4) {
+            err = std::string("weight blob: missing ") + sp.name;
+            return LIC_E_MODEL;
+        }
+        const std::vector<int>& dims = wit->second.first;
+        const std::vector<double>& w = wit->second.second;
+        const std::vector<double>& b = bit->second.second;
+        const int k = dims[2];
+        if (k != sp.k || dims[3] != k) { err = std::string("weight blob: bad kernel size in ") + sp.name; return LIC_E_MODEL; }
+        const int ci = sp.deconv ? dims[0] : dims[1];
+        const int co = sp.deconv ? dims[1] : dims[0];
+        if ((int)b.size() != co) { err = std::string("weight blob: bad bias in ") + sp.name; return LIC_E_MODEL; }
+        L.present = true;
+        L.ld = sp.ld;
+        L.ep = sp.ep;
+        L.k = k;
+        L.deconv = sp.deconv;
+        L.co = co;
+        L.rows = sp.ep == EP_RGB;
+        L.cin = sp.ld == LD_RGB ? 80 : ci;
+        L.cop = L.rows ? 16 : co;
+        if (sp.ld == LD_RGB && ci != 3) { err = "ga0 must take 3 channels"; return LIC_E_MODEL; }
+        if (!L.rows && co % 16 != 0) { err = std::string("channels must be multiples of 16: ") + sp.name; return LIC_E_MODEL; }
+        if (L.rows && co != 3) { err = "gs3 must produce 3 channels"; return LIC_E_MODEL; }
+        // weight accessor in PyTorch layout
+        auto W = [&](int o, int c, int u, int v) -> double {
+            return sp.deconv ? w[(((size_t)c * co + o) * k + u) * k + v] : w[(((size_t)o * ci + c) * k + u) * k + v];
+        };
+
+        // phases and taps
+        std::vector<PhaseDesc> ph;
+        std::vector<std::vector<float>> packed;
+        const int p = k / 2;
+        if (sp.ld == LD_RGB) {
+            PhaseDesc d{};
+            d.ntaps = 1;
+            ph.push_back(d);
+            std::vector<float> wp((size_t)L.cop * 80, 0.0f);
+            for (int o = 0; o < co; ++o)
+                for (int u = 0; u < 5; ++u)
+                    for (int v = 0; v < 5; ++v)
+                        for (int c = 0; c < 3; ++c) wp[(size_t)o * 80 + (u * 5 + v) * 3 + c] = (float)W(o, c, u, v);
+            packed.push_back(std::move(wp));
+        } else if (!sp.deconv) {
+            PhaseDesc d{};
+            d.ntaps = k * k;
+            std::vector<float> wp((size_t)k * k * L.cop * ci, 0.0f);
+            for (int u = 0; u < k; ++u)
+                for (int v = 0; v < k; ++v) {
+                    const int t = u * k + v;
+                    d.dy[t] = (int8_t)(u - p);
+                    d.dx[t] = (int8_t)(v - p);
+                    for (int o = 0; o < co; ++o)
+                        for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + o) * ci + c] = (float)W(o, c, u, v);
+                }
+            ph.push_back(d);
+            packed.push_back(std::move(wp));
+        } else if (!L.rows) {
+            // stride-2 transposed conv: output (2a + py, 2b + px) gathers taps u
+            // with (py + p - u) even from input row a + (py + p - u) / 2
+            for (int py = 0; py < 2; ++py)
+                for (int px = 0; px < 2; ++px) {
+                    PhaseDesc d{};
+                    d.oy = py;
+                    d.ox = px;
+                    std::vector<int> us, vs;
+                    for (int u = 0; u < k; ++u) if (((py + p - u) & 1) == 0) us.push_back(u);
+                    for (int v = 0; v < k; ++v) if (((px + p - v) & 1) == 0) vs.push_back(v);
+                    d.ntaps = (int)(us.size() * vs.size());
+                    std::vector<float> wp((size_t)d.ntaps * L.cop * ci, 0.0f);
+                    int t = 0;
+                    for (int u : us)
+                        for (int v : vs) {
+                            d.dy[t] = (int8_t)((py + p - u) / 2);
+                            d.dx[t] = (int8_t)((px + p - v) / 2);
+                            for (int o = 0; o < co; ++o)
+                                for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + o) * ci + c] = (float)W(o, c, u, v);
+                            ++t;
+                        }
+                    ph.push_back(d);
+                    packed.push_back(std::move(wp));
+                }
+        } else {
+            // transposed conv to 3 channels: all four phases as 12 GEMM rows
+            // r = 3 (2 py + px) + o over a 3x3 input neighbourhood
+            PhaseDesc d{};
+            d.ntaps = 9;
+            std::vector<float> wp((size_t)9 * L.cop * ci, 0.0f);
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const int t = (dy + 1) * 3 + (dx + 1);
+                    d.dy[t] = (int8_t)dy;
+                    d.dx[t] = (int8_t)dx;
+                    for (int py = 0; py < 2; ++py)
+                        for (int px = 0; px < 2; ++px) {
+                            const int u = py + p - 2 * dy, v = px + p - 2 * dx;
+                            if (u < 0 || u >= k || v < 0 || v >= k) continue;
+                            for (int o = 0; o < 3; ++o) {
+                                const int r = 3 * (2 * py + px) + o;
+                                for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + r) * ci + c] = (float)W(o, c, u, v);
+                            }
+                        }
+                }
+            ph.push_back(d);
+            packed.push_back(std::move(wp));
+        }
+        L.nphase = (int)ph.size();
+
+        size_t total = 0;
+        for (auto& v : packed) total += v.size();
+        L.d_w = (float*)dev_alloc(total * sizeof(float));
+        L.d_ph = (PhaseDesc*)dev_alloc(ph.size() * sizeof(PhaseDesc));
+        L.d_bias = (float*)dev_alloc(L.cop * sizeof(float));
+        if (!L.d_w || !L.d_ph || !L.d_bias) { err = "device allocation failed"; return LIC_E_NOMEM; }
+        size_t off = 0;
+        for (size_t i = 0; i < packed.size(); ++i) {
+            HIP_TRY(hipMemcpy(L.d_w + off, packed[i].data(), packed[i].size() * sizeof(float), hipMemcpyHostToDevice));
+            ph[i].w = L.d_w + off;
+            off += packed[i].size();
+        }
+        HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
+        L.host_ph = ph;
+        std::vector<float> bias(L.cop, 0.0f);
+        for (int r = 0; r < L.cop; ++r) {
+            if (L.rows) { if (r < 12) bias[r] = (float)b[r % 3]; }
+            else if (r < co) bias[r] = (float)b[r];
+        }
+        HIP_TRY(hipMemcpy(L.d_bias, bias.data(), L.cop * sizeof(float), hipMemcpyHostToDevice));
+
+        if (sp.ep == EP_GDN || sp.ep == EP_IGDN) {
+            auto git = P.find(std::string(sp.name) + ".gamma");
+            auto beit = P.find(std::string(sp.name) + ".beta");
+            if (git == P.end() || beit == P.end() || git->second.second.size() != (size_t)co * co ||
+                beit->second.second.size() != (size_t)co) {
+                err = std::string("weight blob: GDN parameters missing in ") + sp.name;
+                return LIC_E_MODEL;
+            }
+            std::vector<float> g(git->second.second.begin(), git->second.second.end());
+            std::vector<float> be(beit->second.second.begin(), beit->second.second.end());
+            L.d_gamma = (float*)dev_alloc(g.size() * sizeof(float));
+            L.d_beta = (float*)dev_alloc(be.size() * sizeof(float));
+            if (!L.d_gamma || !L.d_beta) { err = "device allocation failed"; return LIC_E_NOMEM; }
+            HIP_TRY(hipMemcpy(L.d_gamma, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(L.d_beta, be.data(), be.size() * sizeof(float), hipMemcpyHostToDevice));
+        }
+        // offsets: quantisation of y (factorized: channel medians; hyperprior: 0)
+        // and of z (medians); dequantisation in the loaders likewise
+        if (sp.id == LIC_GA3) L.d_qmu = kind == 0 ? d_medians : d_zero;
+        if (sp.id == LIC_HA2) L.d_qmu = d_medians;
+        if (sp.id == LIC_HS0) L.d_mu_in = d_medians;
+        if (sp.id == LIC_GS0) L.d_mu_in = kind == 0 ? d_medians : d_zero;
+    }
+    return LIC_OK;
+}
+
+Geo Codec::geo(int id, const FrameDims& d) const
+{
+    const int Hp = d.Hp, Wp = d.Wp, Hy = d.Hy, Wy = d.Wy, Hz = d.Hz, Wz = d.Wz;
+    switch (id) {
+    case LIC_GA0: return {d.H, d.W, Hp / 2, Wp / 2, 2, Hp / 2, Wp / 2, 1};
+    case LIC_GA1: return {Hp / 2, Wp / 2, Hp / 4, Wp / 4, 2, Hp / 4, Wp / 4, 1};
+    case LIC_GA2: return {Hp / 4, Wp / 4, Hp / 8, Wp / 8, 2, Hp / 8, Wp / 8, 1};
+    case LIC_GA3: return {Hp / 8, Wp / 8, Hy, Wy, 2, Hy, Wy, 1};
+    case LIC_HA0: return {Hy, Wy, Hy, Wy, 1, Hy, Wy, 1};
+    case LIC_HA1: return {Hy, Wy, Hy / 2, Wy / 2, 2, Hy / 2, Wy / 2, 1};
+    case LIC_HA2: return {Hy / 2, Wy / 2, Hz, Wz, 2, Hz, Wz, 1};
+    case LIC_HS0: return {Hz, Wz, Hz, Wz, 1, 2 * Hz, 2 * Wz, 2};
+    case LIC_HS1: return {2 * Hz, 2 * Wz, 2 * Hz, 2 * Wz, 1, Hy, Wy, 2};
+    case LIC_HS2: return {Hy, Wy, Hy, Wy, 1, Hy, Wy, 1};
+    case LIC_GS0: return {Hy, Wy, Hy, Wy, 1, 2 * Hy, 2 * Wy, 2};
+    case LIC_GS1: return {Hp / 8, Wp / 8, Hp / 8, Wp / 8, 1, Hp / 4, Wp / 4, 2};
+    case LIC_GS2: return {Hp / 4, Wp / 4, Hp / 4, Wp / 4, 1, Hp / 2, Wp / 2, 2};
+    case LIC_GS3: return {Hp / 2, Wp / 2, Hp / 2, Wp / 2, 1, Hp, Wp, 2};
+    }
+    return {0, 0, 0, 0, 0, 0, 0, 0};
+}
+
+int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void* out, void* aux, hipStream_t s,
+                        std::string* errp)
+{
+    if (id < 0 || id >= LIC_NUM_LAYERS || !layers[id].present) { *errp = "layer not present in this model"; return LIC_E_ARG; }
+    const LayerGPU& L = layers[id];
+    const Geo g = geo(id, d);
+    ConvArgs a{};
+    a.in = in;
+    a.out = out;
+    a.aux = aux;
+    a.ph = L.d_ph;
+    a.bias = L.d_bias;
+    a.mu_in = L.d_mu_in;
+    a.gamma = L.d_gamma;
+    a.beta = L.d_beta;
+    a.qmu = L.d_qmu;
+    a.thr = d_thr;
+    a.n = n;
+    a.Hin = g.Hin;
+    a.Win = g.Win;
+    a.Hg = g.Hg;
+    a.Wg = g.Wg;
+    a.s_in = g.s_in;
+    a.Hout = g.Hout;
+    a.Wout = g.Wout;
+    a.s_out = g.s_out;
+    a.Co = L.co;
+    a.nphase = L.nphase;
+    a.hs_exp = hs_exp;
+    a.Hc = d.H;
+    a.Wc = d.W;
+
+    KernelKey key{L.cin, 0, 0, 0, L.ld, L.ep};
+    const long pixels = (long)n * g.Hg * g.Wg;
+    if (L.ep == EP_GDN || L.ep == EP_IGDN) {
+        key.mt = L.co / 16;
+        key.nt = key.mt <= 8 ? 2 : 1;
+        key.waves = 4;
+        a.ncog = 1;
+    } else if (L.ep == EP_RGB) {
+        key.mt = 1;
+        key.nt = 4;
+        key.waves = 4;
+        a.ncog = 1;
+    } else {
+        // large tiles when they still give the chip >= 4 waves per CU
+        const long big_waves = ((pixels + 31) / 32) * L.nphase * (L.cop / 64);
+        if (L.cop % 64 == 0 && big_waves >= 1024) {
+            key.mt = 4; key.nt = 2; key.waves = 4;
+        } else {
+            key.mt = 1; key.nt = 1; key.waves = 1;
+        }
+        a.ncog = L.cop / (16 * key.mt);
+    }
+    const long per_block = (long)key.waves * key.nt * 16;
+    const long tiles = (pixels + per_block - 1) / per_block;
+    const long nblocks = tiles * L.nphase * a.ncog;
+    if (nblocks <= 0) return LIC_OK;
+    if (nblocks > (1L << 30)) { *errp = "launch too large"; return LIC_E_BUDGET; }
+    hipError_t e = launch_conv(key, a, (int)nblocks, s);
+    if (e != hipSuccess) {
+        *errp = std::string("kernel launch failed: ") + hipGetErrorString(e);
+        return LIC_E_HIP;
+    }
+    return LIC_OK;
+}
+
+}  // namespace lic
