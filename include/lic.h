@@ -85,8 +85,8 @@ int codec_create(const codec_config* cfg, const void* weight_blob, size_t blob_l
 
 /* Encodes n frames (pipelined).  x: n x 3 x H x W float32, host or device.
  * Bitstreams are written back to back into out[0..cap); lens[i] receives the
- * length of frame i.  On LIC_E_SMALLBUF nothing is written to out and lens[]
- * holds each frame's size. */
+ * length of frame i.  On LIC_E_SMALLBUF lens[] holds each frame's size and
+ * the contents of out are unspecified. */
 int codec_encode(codec_t* c, const float* x, int n, int H, int W, int is_device,
                  uint8_t* out, size_t cap, size_t* lens);
 
@@ -147,6 +147,13 @@ enum {
 };
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
                     const void* in, void* out, void* aux);
+
+/* Kernel timing inside the pipeline: every launch of a layer whose bit is
+ * set in mask (bit i = layer i) is bracketed with HIP events on the stream
+ * it runs on; the accumulators are reset.  codec_layer_time returns the
+ * summed kernel time (ms) and launch count of one layer since then. */
+int codec_time_layers(codec_t* c, uint32_t mask);
+int codec_layer_time(codec_t* c, int layer, double* total_ms, long* launches);
 
 /* Entropy tables the codec built at create (host copies, for checking):
  * which 0 = factorized tables [C][129] (C = N for the hyperprior's z, M for

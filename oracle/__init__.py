@@ -70,6 +70,10 @@ def lib():
         L.or_deconv2d_at.argtypes = [P, i, i, i, P, P, i, i, i, i, i, i, i]
         L.or_deconv2d.restype = None
         L.or_deconv2d.argtypes = [P, i, i, i, P, P, i, i, i, i, P, i, i]
+        L.or_conv2d_points.restype = None
+        L.or_conv2d_points.argtypes = [P, i, i, i, P, P, i, i, i, i, i, P, P]
+        L.or_deconv2d_points.restype = None
+        L.or_deconv2d_points.argtypes = [P, i, i, i, P, P, i, i, i, i, i, P, P]
         L.or_gdn.restype = None
         L.or_gdn.argtypes = [P, i, l, P, P, i, P]
         L.or_density_logit.restype = d
@@ -150,6 +154,33 @@ def deconv2d_at(x, w, b, s: int, p: int, o: int, i: int, j: int) -> float:
                                 s, p, o, i, j)
 
 
+def conv2d_points(x, w, b, s: int, p: int, pts) -> np.ndarray:
+    """Every output channel of a convolution at output positions pts [(i, j)]:
+    returns [len(pts), C_out].  Each value is the single-output definition."""
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    Co, _, k, _ = w.shape
+    ij = np.ascontiguousarray(pts, np.int32).reshape(-1, 2)
+    out = np.empty((ij.shape[0], Co), np.float64)
+    lib().or_conv2d_points(_p(x), C, H, W, _p(w), None if b is None else _p(b), Co, k, s, p, ij.shape[0],
+                           _p(ij), _p(out))
+    return out
+
+
+def deconv2d_points(x, w, b, s: int, p: int, pts) -> np.ndarray:
+    """Every output channel of a transposed convolution at output positions pts."""
+    x, w = _f64(x), _f64(w)
+    b = None if b is None else _f64(b)
+    C, H, W = x.shape
+    _, Co, k, _ = w.shape
+    ij = np.ascontiguousarray(pts, np.int32).reshape(-1, 2)
+    out = np.empty((ij.shape[0], Co), np.float64)
+    lib().or_deconv2d_points(_p(x), C, H, W, _p(w), None if b is None else _p(b), Co, k, s, p, ij.shape[0],
+                             _p(ij), _p(out))
+    return out
+
+
 def gdn(x, beta, gamma, inverse: bool = False) -> np.ndarray:
     """GDN y_i = x_i / sqrt(beta_i + sum_j gamma_ij x_j^2); IGDN multiplies instead."""
     x = _f64(x)
@@ -215,7 +246,7 @@ def scale_index_f32(v32, hs_out: int) -> np.ndarray:
     t = scale_table()
     v = np.asarray(v32, np.float32).reshape(-1, 1)
     if hs_out == 1:
-        lt = np.log(t[:63]).astype(np.float32)
+        lt = np.array([math.log(tk) for tk in t[:63]], np.float64).astype(np.float32)
         cnt = np.sum(lt[None, :] < v, axis=1)
     else:
         t32 = t.astype(np.float32)

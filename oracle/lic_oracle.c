@@ -103,6 +103,27 @@ void or_deconv2d(const double* in, int C, int H, int W,
                 out[((long)o * Ho + i) * Wo + j] = or_deconv2d_at(in, C, H, W, w, b, Co, k, s, p, o, i, j);
 }
 
+/* All output channels at a list of output positions (i, j): out[n][Co]. */
+void or_conv2d_points(const double* in, int C, int H, int W,
+                      const double* w, const double* b, int Co, int k, int s, int p,
+                      int npts, const int* ij, double* out)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < npts; ++q)
+        for (int o = 0; o < Co; ++o)
+            out[(long)q * Co + o] = or_conv2d_at(in, C, H, W, w, b, k, s, p, o, ij[2 * q], ij[2 * q + 1]);
+}
+
+void or_deconv2d_points(const double* in, int C, int H, int W,
+                        const double* w, const double* b, int Co, int k, int s, int p,
+                        int npts, const int* ij, double* out)
+{
+#pragma omp parallel for schedule(dynamic)
+    for (int q = 0; q < npts; ++q)
+        for (int o = 0; o < Co; ++o)
+            out[(long)q * Co + o] = or_deconv2d_at(in, C, H, W, w, b, Co, k, s, p, o, ij[2 * q], ij[2 * q + 1]);
+}
+
 /* ------------------------------------------------------------------------ */
 /* GDN / IGDN, per pixel over channels.  x and out are [C][HW] planes.      */
 /*   n_i = beta_i + sum_j gamma[i][j] x_j^2                                 */

@@ -139,6 +139,20 @@ class Codec:
         self._check(lib.codec_get_stats(self._h, buf, 4096))
         return json.loads(buf.value.decode())
 
+    def time_layers(self, layers):
+        """Bracket every pipeline launch of these layers with HIP events."""
+        mask = 0
+        for L in layers or ():
+            mask |= 1 << (_lib.LAYER_ID[L] if isinstance(L, str) else int(L))
+        self._check(lib.codec_time_layers(self._h, mask))
+
+    def layer_time(self, layer):
+        """(summed kernel milliseconds, launches) of a timed layer."""
+        lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
+        ms, n = ctypes.c_double(), ctypes.c_long()
+        self._check(lib.codec_layer_time(self._h, lid, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
     def tables(self, which: int) -> np.ndarray:
         buf = np.zeros(512 * 129, np.uint32)
         n = self._check(lib.codec_tables(self._h, which, buf.ctypes.data, buf.size))

@@ -262,6 +262,28 @@ int codec_run_layer(codec_t* c, int layer, int n, int H, int W, const void* in, 
     return LIC_OK;
 }
 
+int codec_time_layers(codec_t* c, uint32_t mask)
+{
+    if (!c) return LIC_E_ARG;
+    if (mask >> LIC_NUM_LAYERS) return fail(c, LIC_E_ARG, "no such layer");
+    std::lock_guard<std::mutex> g(c->lt_m);
+    c->timed_mask.store(mask);
+    for (int l = 0; l < LIC_NUM_LAYERS; ++l) {
+        c->layer_ms[l] = 0.0;
+        c->layer_launches[l] = 0;
+    }
+    return LIC_OK;
+}
+
+int codec_layer_time(codec_t* c, int layer, double* total_ms, long* launches)
+{
+    if (!c || !total_ms || !launches || layer < 0 || layer >= LIC_NUM_LAYERS) return LIC_E_ARG;
+    std::lock_guard<std::mutex> g(c->lt_m);
+    *total_ms = c->layer_ms[layer];
+    *launches = c->layer_launches[layer];
+    return LIC_OK;
+}
+
 long codec_tables(const codec_t* c, int which, uint32_t* freq, size_t cap)
 {
     if (!c || !freq) return LIC_E_ARG;

@@ -189,6 +189,10 @@ struct GpuStage {
     BlockingQueue<Task*> queue;
     std::thread thread;
     double busy_s = 0.0;
+    // events bracketing timed layers: [in-flight task][layer][start/end]
+    int cur = 0;
+    hipEvent_t lev[2][LIC_NUM_LAYERS][2] = {};
+    bool lrec[2][LIC_NUM_LAYERS] = {};
 };
 
 struct Codec {
@@ -221,6 +225,11 @@ struct Codec {
     int last_frames = 0;
     std::atomic<long> cpu_busy_us{0};
     bool started = false;
+    // kernel timing of selected layers inside the pipeline (HIP events)
+    std::atomic<uint32_t> timed_mask{0};
+    std::mutex lt_m;
+    double layer_ms[LIC_NUM_LAYERS] = {};
+    long layer_launches[LIC_NUM_LAYERS] = {};
 
     ~Codec();
     // model

@@ -22,6 +22,7 @@
 // GDN contraction over channels needs - no data movement between the two.
 #include <hip/hip_runtime.h>
 
+#include "../../include/lic.h"
 #include "conv_args.h"
 #include "kernels.h"
 
@@ -45,7 +46,9 @@ __device__ __forceinline__ int xcd_logical_tile(int L, int T)
     return prefix + slot;
 }
 
-template <int CIN, int MT, int NT, int WAVES, int LD, int EP>
+// TAG is the layer id: it changes no code but gives every layer its own
+// kernel symbol, so profiles attribute time per layer.
+template <int TAG, int CIN, int MT, int NT, int WAVES, int LD, int EP>
 __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
 {
     constexpr int KC = CIN / 16;
@@ -318,30 +321,31 @@ struct KernelEntry {
     void (*fn)(ConvArgs);
 };
 
-#define LIC_K(CIN, MT, NT, WV, LD, EP) \
-    {{CIN, MT, NT, WV, LD, EP}, conv_igemm_f32<CIN, MT, NT, WV, LD, EP>}
+#define LIC_K(TAG, CIN, MT, NT, WV, LD, EP) \
+    {{TAG, CIN, MT, NT, WV, LD, EP}, conv_igemm_f32<TAG, CIN, MT, NT, WV, LD, EP>}
+// both tile configurations of a non-GDN layer: large (4 m-tiles x 2 n-tiles,
+// 4 waves) and small (1 x 1, one wave) for grids too small to fill the chip
+#define LIC_K2(TAG, CIN, LD, EP) LIC_K(TAG, CIN, 4, 2, 4, LD, EP), LIC_K(TAG, CIN, 1, 1, 1, LD, EP)
 
 static const KernelEntry kEntries[] = {
-    // GDN / IGDN layers: one wave holds every channel of its pixels
-    LIC_K(80, 8, 2, 4, LD_RGB, EP_GDN), LIC_K(80, 12, 1, 4, LD_RGB, EP_GDN),
-    LIC_K(128, 8, 2, 4, LD_F32, EP_GDN), LIC_K(192, 12, 1, 4, LD_F32, EP_GDN),
-    LIC_K(192, 8, 2, 4, LD_I8, EP_IGDN), LIC_K(320, 12, 1, 4, LD_I8, EP_IGDN),
-    LIC_K(128, 8, 2, 4, LD_F32, EP_IGDN), LIC_K(192, 12, 1, 4, LD_F32, EP_IGDN),
-    // latent quantisation (g_a last layer, h_a last layer)
-    LIC_K(128, 4, 2, 4, LD_F32, EP_QUANT), LIC_K(192, 4, 2, 4, LD_F32, EP_QUANT),
-    LIC_K(128, 1, 1, 1, LD_F32, EP_QUANT), LIC_K(192, 1, 1, 1, LD_F32, EP_QUANT),
-    // ReLU layers of h_a / h_s
-    LIC_K(192, 4, 2, 4, LD_F32_ABS, EP_RELU), LIC_K(320, 4, 2, 4, LD_F32_ABS, EP_RELU),
-    LIC_K(192, 1, 1, 1, LD_F32_ABS, EP_RELU), LIC_K(320, 1, 1, 1, LD_F32_ABS, EP_RELU),
-    LIC_K(128, 4, 2, 4, LD_F32, EP_RELU), LIC_K(192, 4, 2, 4, LD_F32, EP_RELU),
-    LIC_K(128, 1, 1, 1, LD_F32, EP_RELU), LIC_K(192, 1, 1, 1, LD_F32, EP_RELU),
-    LIC_K(128, 4, 2, 4, LD_I8, EP_RELU), LIC_K(192, 4, 2, 4, LD_I8, EP_RELU),
-    LIC_K(128, 1, 1, 1, LD_I8, EP_RELU), LIC_K(192, 1, 1, 1, LD_I8, EP_RELU),
-    // scale-table index (h_s last layer)
-    LIC_K(128, 4, 2, 4, LD_F32, EP_INDEX), LIC_K(192, 4, 2, 4, LD_F32, EP_INDEX),
-    LIC_K(128, 1, 1, 1, LD_F32, EP_INDEX), LIC_K(192, 1, 1, 1, LD_F32, EP_INDEX),
-    // final transposed convolution to RGB
-    LIC_K(128, 1, 4, 4, LD_F32, EP_RGB), LIC_K(192, 1, 4, 4, LD_F32, EP_RGB),
+    // g_a: GDN layers hold every channel of their pixels in one wave
+    LIC_K(LIC_GA0, 80, 8, 2, 4, LD_RGB, EP_GDN), LIC_K(LIC_GA0, 80, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_K(LIC_GA1, 128, 8, 2, 4, LD_F32, EP_GDN), LIC_K(LIC_GA1, 192, 12, 1, 4, LD_F32, EP_GDN),
+    LIC_K(LIC_GA2, 128, 8, 2, 4, LD_F32, EP_GDN), LIC_K(LIC_GA2, 192, 12, 1, 4, LD_F32, EP_GDN),
+    LIC_K2(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2(LIC_GA3, 192, LD_F32, EP_QUANT),
+    // h_a
+    LIC_K2(LIC_HA0, 192, LD_F32_ABS, EP_RELU), LIC_K2(LIC_HA0, 320, LD_F32_ABS, EP_RELU),
+    LIC_K2(LIC_HA1, 128, LD_F32, EP_RELU), LIC_K2(LIC_HA1, 192, LD_F32, EP_RELU),
+    LIC_K2(LIC_HA2, 128, LD_F32, EP_QUANT), LIC_K2(LIC_HA2, 192, LD_F32, EP_QUANT),
+    // h_s
+    LIC_K2(LIC_HS0, 128, LD_I8, EP_RELU), LIC_K2(LIC_HS0, 192, LD_I8, EP_RELU),
+    LIC_K2(LIC_HS1, 128, LD_F32, EP_RELU), LIC_K2(LIC_HS1, 192, LD_F32, EP_RELU),
+    LIC_K2(LIC_HS2, 128, LD_F32, EP_INDEX), LIC_K2(LIC_HS2, 192, LD_F32, EP_INDEX),
+    // g_s
+    LIC_K(LIC_GS0, 192, 8, 2, 4, LD_I8, EP_IGDN), LIC_K(LIC_GS0, 320, 12, 1, 4, LD_I8, EP_IGDN),
+    LIC_K(LIC_GS1, 128, 8, 2, 4, LD_F32, EP_IGDN), LIC_K(LIC_GS1, 192, 12, 1, 4, LD_F32, EP_IGDN),
+    LIC_K(LIC_GS2, 128, 8, 2, 4, LD_F32, EP_IGDN), LIC_K(LIC_GS2, 192, 12, 1, 4, LD_F32, EP_IGDN),
+    LIC_K(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_K(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
 };
 
 bool kernel_available(const KernelKey& k)

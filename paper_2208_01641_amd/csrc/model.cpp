@@ -427,7 +427,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.Hc = d.H;
     a.Wc = d.W;
 
-    KernelKey key{L.cin, 0, 0, 0, L.ld, L.ep};
+    KernelKey key{id, L.cin, 0, 0, 0, L.ld, L.ep};
     const long pixels = (long)n * g.Hg * g.Wg;
     if (L.ep == EP_GDN || L.ep == EP_IGDN) {
         key.mt = L.co / 16;

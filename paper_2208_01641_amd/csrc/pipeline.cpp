@@ -41,8 +41,14 @@ double now_s()
 
 #define LAUNCH(layer, nimg, in, out, aux, stream)                                  \
     do {                                                                           \
+        const bool timed_ = (timed_mask.load() >> (layer)) & 1u;                    \
+        if (timed_) hipEventRecord(G.lev[G.cur][layer][0], stream);                \
         int r_ = launch_layer(layer, nimg, d, in, out, aux, stream, &t->err);      \
         if (r_ != LIC_OK) return r_;                                               \
+        if (timed_) {                                                              \
+            hipEventRecord(G.lev[G.cur][layer][1], stream);                        \
+            G.lrec[G.cur][layer] = true;                                           \
+        }                                                                          \
     } while (0)
 
 static int stage_gpu_index(StageKind k)
@@ -220,6 +226,10 @@ void Codec::gpu_loop(int gi)
     for (int i = 0; i < 2; ++i) {
         hipEventCreate(&ev_start[i]);
         hipEventCreate(&ev_end[i]);
+        for (int l = 0; l < LIC_NUM_LAYERS; ++l) {
+            hipEventCreate(&G.lev[i][l][0]);
+            hipEventCreate(&G.lev[i][l][1]);
+        }
     }
     Task* pending = nullptr;
     int pend_ev = 0, cur_ev = 0;
@@ -230,6 +240,16 @@ void Codec::gpu_loop(int gi)
         }
         float ms = 0.0f;
         if (hipEventElapsedTime(&ms, ev_start[e], ev_end[e]) == hipSuccess) G.busy_s += ms * 1e-3;
+        for (int l = 0; l < LIC_NUM_LAYERS; ++l) {
+            if (!G.lrec[e][l]) continue;
+            float lms = 0.0f;
+            if (hipEventElapsedTime(&lms, G.lev[e][l][0], G.lev[e][l][1]) == hipSuccess) {
+                std::lock_guard<std::mutex> g(lt_m);
+                layer_ms[l] += lms;
+                layer_launches[l]++;
+            }
+            G.lrec[e][l] = false;
+        }
         advance(t);
     };
     for (;;) {
@@ -244,6 +264,7 @@ void Codec::gpu_loop(int gi)
             break;
         }
         hipEventRecord(ev_start[cur_ev], G.stream);
+        G.cur = cur_ev;
         int rc = G.kind == ST_GPU_ENC ? gpu_encode(t, G) : G.kind == ST_GPU_HS ? gpu_hs(t, G) : gpu_gs(t, G);
         if (rc != LIC_OK) t->status = rc;
         hipEventRecord(ev_end[cur_ev], G.stream);
@@ -256,6 +277,10 @@ void Codec::gpu_loop(int gi)
     for (int i = 0; i < 2; ++i) {
         hipEventDestroy(ev_start[i]);
         hipEventDestroy(ev_end[i]);
+        for (int l = 0; l < LIC_NUM_LAYERS; ++l) {
+            hipEventDestroy(G.lev[i][l][0]);
+            hipEventDestroy(G.lev[i][l][1]);
+        }
     }
 }
 
