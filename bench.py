@@ -9,7 +9,13 @@ GPU synthesis transform with IGDN) back to a reconstructed frame.  Frames
 are pipelined through the library's runtime (encoder chained into decoder
 per frame); the input frames are resident in device memory before timing.
 
-Prints one JSON line (see the key list at the bottom of main()).
+The headline line is the FP32 form at N=128, M=192.  Unless --no-variants
+is given, the same JSON line also carries the comparison runs ("variants"):
+the unpipelined per-frame form (one frame in flight), the BF16 form at
+720p, and the FP32 / BF16 forms of the 1080p N=192 M=320 batch-4 workload,
+each with frames/s, p50/p99 latency, PSNR and bits per pixel.
+
+Prints one JSON line.
 """
 import argparse
 import hashlib
@@ -23,18 +29,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "720p hyperprior enc+dec frames/s + p99 ms; BF16/FP8 vs FP32 at fixed PSNR"
-PEAK = {"mfma_fp32": 157.3, "hbm": 8000.0}     # TFLOP/s, GB/s (MI355X published)
-N, M = 128, 192
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_01641_amd", "csrc", "conv_kernels.hip")
+LAYERS = ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3")
 
 
-def layer_flops(layer, H, W):
-    """Algorithmic FLOPs (2 x MAC) of one launch of a layer on one frame,
-    on the 64-multiple padded frame the method codes."""
+def layer_flops(layer, H, W, N, M):
+    """Algorithmic FLOPs (2 x MAC) of one layer on one frame, on the
+    64-multiple padded frame the method codes (GDN contraction included)."""
     Hp, Wp = 64 * math.ceil(H / 64), 64 * math.ceil(W / 64)
     Hy, Wy = Hp // 16, Wp // 16
-    conv = {  # (output pixels or input pixels for transposed convs, C_in, C_out, k*k)
+    conv = {  # (output pixels, or input pixels for transposed convs, C_in, C_out, k*k)
         "GA0": (Hp // 2 * Wp // 2, 3, N, 25), "GA1": (Hp // 4 * Wp // 4, N, N, 25),
         "GA2": (Hp // 8 * Wp // 8, N, N, 25), "GA3": (Hy * Wy, N, M, 25),
         "HA0": (Hy * Wy, M, N, 9), "HA1": (Hy // 2 * Wy // 2, N, N, 25), "HA2": (Hy // 4 * Wy // 4, N, N, 25),
@@ -45,8 +51,7 @@ def layer_flops(layer, H, W):
     mac = conv[0] * conv[1] * conv[2] * conv[3]
     gdn_px = {"GA0": Hp // 2 * Wp // 2, "GA1": Hp // 4 * Wp // 4, "GA2": Hp // 8 * Wp // 8,
               "GS0": Hp // 8 * Wp // 8, "GS1": Hp // 4 * Wp // 4, "GS2": Hp // 2 * Wp // 2}.get(layer, 0)
-    mac += gdn_px * N * N
-    return 2.0 * mac
+    return 2.0 * (mac + gdn_px * N * N)
 
 
 def kernel_src_hash():
@@ -68,7 +73,7 @@ def traffic_for(layer):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
-def cpu_baseline(x_np, P, blob):
+def cpu_baseline(x_np, P, blob, N, M):
     """The FP64 oracle on the host cores, on a 384x640 crop of one frame
     (a quarter of the padded 768x1280 area), scaled to frames/s."""
     import oracle
@@ -81,8 +86,72 @@ def cpu_baseline(x_np, P, blob):
     scale = (768 * 1280) / (384 * 640)
     cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     return {"value": 1.0 / (dt * scale), "unit": "frames/s", "cores": cores, "kind": "oracle",
-            "sample": f"FP64 oracle encode+decode of one 3x384x640 crop (1/4 of the padded 720p frame area, "
-                      f"{dt:.1f} s wall on {cores} OpenMP threads), scaled x{scale:.0f}"}
+            "sample": f"FP64 oracle encode+decode of one 3x384x640 crop of a frame (1/4 of the padded "
+                      f"720p area, {dt:.1f} s wall on {cores} OpenMP threads), scaled x{scale:.0f}"}
+
+
+def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflight, slices, zero_copy,
+                 timed_layers, copy_probe_mib=0):
+    """Creates a codec, pipelines warmup + steps frames through encode->decode
+    and returns the measurements (and the first frame for the CPU baseline)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_01641_amd import Codec
+
+    P = synth.model_params(1, N, M)
+    blob = synth.weight_blob(P, 1, N, M)
+    codec = Codec(blob, kind=1, N=N, M=M, hs_out=1, precision=precision, y_slices=slices,
+                  entropy_threads=threads, zero_copy=zero_copy, max_in_flight=inflight, max_h=H, max_w=W,
+                  max_batch=batch)
+    frames = synth.frames_sinusoid_torch(H, W, range(steps + warmup), device="cuda")
+    out = torch.empty_like(frames)
+    if copy_probe_mib:
+        src = torch.ones(copy_probe_mib << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if warmup:
+        codec.encode_decode(frames[steps:], out[steps:])
+    codec.time_layers(timed_layers)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bits = codec.encode_decode(frames[:steps], out[:steps])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    lat = codec.latencies_ms()
+    st = codec.stats()
+    layers = {}
+    for L in timed_layers:
+        ms, n = codec.layer_time(L)
+        if n:
+            per_launch = ms / n
+            flops = layer_flops(L, H, W, N, M) * batch      # a launch covers one task of `batch` frames
+            layers[L] = {"avg_us": 1e3 * per_launch, "launches": n, "tflops": flops / (per_launch * 1e-3) / 1e12,
+                         "flops_per_launch": flops}
+    mse = torch.mean((out[:steps] - frames[:steps]) ** 2, dim=(1, 2, 3))
+    res = {
+        "fps": steps / dt,
+        "ms_per_step": 1e3 * dt / steps,
+        "p50_ms": float(np.percentile(lat, 50)),
+        "p99_ms": float(np.percentile(lat, 99)),
+        "psnr_db": float(torch.mean(10 * torch.log10(1.0 / mse)).item()),
+        "bpp": float(np.mean([8.0 * len(b) / (H * W) for b in bits])),
+        "gpu_busy_s": st["gpu_busy_s"],
+        "cpu_busy_s": st["cpu_busy_s"],
+        "layers": layers,
+    }
+    codec.close()
+    x0 = frames[0].cpu().numpy()
+    del frames, out
+    torch.cuda.empty_cache()
+    return res, x0, P, blob
+
+
+def _round(d, nd=3):
+    return {k: (round(v, nd) if isinstance(v, float) else v) for k, v in d.items()}
 
 
 def main():
@@ -92,12 +161,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=30, help="untimed frames first")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
+    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
     ap.add_argument("--threads", type=int, default=0, help="entropy worker threads (0: min(16, cores))")
-    ap.add_argument("--inflight", type=int, default=6, help="frames in flight (pooled slots)")
+    ap.add_argument("--inflight", type=int, default=6, help="tasks in flight (pooled slots)")
     ap.add_argument("--slices", type=int, default=8, help="rANS row slices of y")
-    ap.add_argument("--zero-copy", type=int, default=0)
-    ap.add_argument("--serial", action="store_true", help="one frame in flight (unpipelined baseline)")
+    ap.add_argument("--zero-copy", type=int, default=1)
+    ap.add_argument("--serial", action="store_true", help="one frame in flight (unpipelined)")
     ap.add_argument("--all-layers", action="store_true", help="time every layer (per-layer breakdown)")
+    ap.add_argument("--no-variants", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
@@ -105,96 +176,82 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported by this build "
-              "(frames are independent keyframes: more GPUs would each run their own streams)", file=sys.stderr)
+              "(frames are independent keyframes: each GPU would run its own codec)", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
-
-    import synth
-    from paper_2208_01641_amd import Codec
-
     assert torch.cuda.is_available(), "bench.py needs the GPU"
-    H, W, K, Wm = args.height, args.width, args.steps, args.warmup
     threads = args.threads or min(16, os.cpu_count() or 1)
-    P = synth.model_params(1, N, M)
-    blob = synth.weight_blob(P, 1, N, M)
-    inflight = 1 if args.serial else args.inflight
-    codec = Codec(blob, kind=1, N=N, M=M, hs_out=1, y_slices=args.slices, entropy_threads=threads,
-                  zero_copy=args.zero_copy, max_in_flight=inflight, max_h=H, max_w=W)
+    prec = 1 if args.precision == "bf16" else 0
+    H, W, K, Wm = args.height, args.width, args.steps, args.warmup
+    N, M = 128, 192
+    timed = list(LAYERS) if args.all_layers else ["GA1", "GS2"]
+    main_res, x0, P, blob = run_workload(
+        H=H, W=W, N=N, M=M, precision=prec, batch=1, steps=K, warmup=Wm, threads=threads,
+        inflight=1 if args.serial else args.inflight, slices=args.slices, zero_copy=args.zero_copy,
+        timed_layers=timed, copy_probe_mib=args.copy_probe_mib)
 
-    # inputs resident in HBM: K + W distinct frames of a moving sinusoid field
-    frames = synth.frames_sinusoid_torch(H, W, range(K + Wm), device="cuda")
-    out = torch.empty_like(frames)
-    timed_layers = [l for l in ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2",
-                                "GS0", "GS1", "GS2", "GS3")] if args.all_layers else ["GA1", "GS2"]
-
-    if args.copy_probe_mib:
-        src = torch.ones(args.copy_probe_mib << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
-    if Wm:
-        codec.encode_decode(frames[K:K + Wm], out[K:K + Wm])
-    codec.time_layers(timed_layers)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    bits = codec.encode_decode(frames[:K], out[:K])
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    lat = codec.latencies_ms()
-    st = codec.stats()
-
-    per_layer = {}
-    for L in timed_layers:
-        ms, n = codec.layer_time(L)
-        if n:
-            per_layer[L] = {"avg_us": 1e3 * ms / n, "launches": n,
-                            "tflops": layer_flops(L, H, W) / (ms / n * 1e-3) / 1e12}
+    per_layer = main_res["layers"]
     dom = max(per_layer, key=lambda L: per_layer[L]["avg_us"] * per_layer[L]["launches"])
+    peak = PEAK_TFLOPS["bf16" if prec else "f32"]
     ach = per_layer[dom]["tflops"]
-    roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": PEAK["mfma_fp32"], "unit": "TFLOP/s",
-                "frac": round(ach / PEAK["mfma_fp32"], 4), "traffic": traffic_for(dom),
+    roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
+                "frac": round(ach / peak, 4), "traffic": traffic_for(dom) if not prec else None,
                 "kernel": dom, "avg_us": round(per_layer[dom]["avg_us"], 2),
-                "flops_per_launch": layer_flops(dom, H, W)}
-
-    # quality of the timed run (GPU-side summary: PSNR against the input, bpp)
-    mse = torch.mean((out[:K] - frames[:K]) ** 2, dim=(1, 2, 3))
-    psnr = float(torch.mean(10 * torch.log10(1.0 / mse)).item())
-    bpp = float(np.mean([8.0 * len(b) / (H * W) for b in bits]))
+                "flops_per_launch": per_layer[dom]["flops_per_launch"]}
 
     res = {
         "metric": METRIC,
-        "value": round(K / dt, 3),
+        "value": round(main_res["fps"], 3),
         "unit": "frames/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": round(1e3 * dt / K, 4),
+        "ms_per_step": round(main_res["ms_per_step"], 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16" if prec else "f32",
         "data": "synthetic",
-        "config": {"workload": f"scale-hyperprior N={N} M={M} FP32 encode chained into decode, "
+        "config": {"workload": f"scale-hyperprior N={N} M={M} {args.precision.upper()} encode chained into decode, "
                                f"3x{H}x{W} frames (32 moving sinusoids + noise), pipelined",
-                   "frames": K, "entropy_threads": threads, "max_in_flight": inflight, "y_slices": args.slices,
-                   "zero_copy": args.zero_copy},
-        "p50_ms": round(float(np.percentile(lat, 50)), 3),
-        "p99_ms": round(float(np.percentile(lat, 99)), 3),
-        "psnr_db": round(psnr, 3),
-        "bpp": round(bpp, 4),
-        "gpu_busy_s": st["gpu_busy_s"],
-        "cpu_busy_s": st["cpu_busy_s"],
+                   "frames": K, "entropy_threads": threads, "max_in_flight": 1 if args.serial else args.inflight,
+                   "y_slices": args.slices, "zero_copy": args.zero_copy},
+        "p50_ms": round(main_res["p50_ms"], 3),
+        "p99_ms": round(main_res["p99_ms"], 3),
+        "psnr_db": round(main_res["psnr_db"], 3),
+        "bpp": round(main_res["bpp"], 4),
+        "gpu_busy_s": main_res["gpu_busy_s"],
+        "cpu_busy_s": main_res["cpu_busy_s"],
         "layers": {L: {"avg_us": round(v["avg_us"], 2), "tflops": round(v["tflops"], 2)} for L, v in per_layer.items()},
         "roofline": roofline,
+        "variants": None,
         "cpu_baseline": None,
     }
-    codec.close()
+
+    if not args.no_variants:
+        var = {}
+        common = dict(threads=threads, slices=args.slices, zero_copy=args.zero_copy, timed_layers=["GA1", "GS2"])
+        r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=0, batch=1, steps=60, warmup=5,
+                                  inflight=1, **common)
+        var["fp32_720p_one_frame_in_flight"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=1, batch=1, steps=300, warmup=30,
+                                  inflight=args.inflight, **common)
+        var["bf16_720p"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        var["bf16_720p"]["d_psnr_db_vs_fp32"] = round(r["psnr_db"] - main_res["psnr_db"], 4)
+        var["bf16_720p"]["d_bpp_vs_fp32"] = round(r["bpp"] - main_res["bpp"], 5)
+        big = {}
+        for name, p in (("fp32", 0), ("bf16", 1)):
+            r, _, _, _ = run_workload(H=1080, W=1920, N=192, M=320, precision=p, batch=4, steps=40, warmup=8,
+                                      inflight=3, **common)
+            big[name] = r
+            var[f"{name}_1080p_n192_m320_batch4"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        var["bf16_1080p_n192_m320_batch4"]["d_psnr_db_vs_fp32"] = round(big["bf16"]["psnr_db"] - big["fp32"]["psnr_db"], 4)
+        var["bf16_1080p_n192_m320_batch4"]["d_bpp_vs_fp32"] = round(big["bf16"]["bpp"] - big["fp32"]["bpp"], 5)
+        res["variants"] = var
+
     if not args.no_cpu_baseline:
-        x0 = frames[0].cpu().numpy()
-        res["cpu_baseline"] = cpu_baseline(x0, P, blob)
+        res["cpu_baseline"] = cpu_baseline(x0, P, blob, N, M)
     print(json.dumps(res), flush=True)
 
 

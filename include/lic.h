@@ -50,7 +50,7 @@ typedef enum {
 } lic_status;
 
 enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1 };
-enum { LIC_PREC_FP32 = 0 };
+enum { LIC_PREC_FP32 = 0, LIC_PREC_BF16 = 1 };
 enum { LIC_HS_RELU = 0, LIC_HS_EXP = 1 };
 
 /* Creation parameters.  Fill with codec_default_config() first. */
@@ -58,7 +58,10 @@ typedef struct {
     uint32_t struct_size;      /* sizeof(codec_config), for ABI versioning           */
     int32_t  kind;             /* LIC_KIND_*: factorized prior [1] or hyperprior [2] */
     int32_t  N, M;             /* transform / latent channels (128/192 or 192/320)   */
-    int32_t  precision;        /* LIC_PREC_FP32                                      */
+    int32_t  precision;        /* LIC_PREC_FP32, or LIC_PREC_BF16: g_a / g_s GEMM    */
+                               /* operands and their activations in bf16 (FP32    */
+                               /* accumulation, FP32 GDN/IGDN); h_a, h_s, the     */
+                               /* quantisers and the scale index stay FP32        */
     int32_t  hs_out;           /* output activation of h_s: LIC_HS_EXP or _RELU      */
     int32_t  gs_mode;          /* 0: full synthesis transform                        */
     int32_t  y_slices;         /* S >= 1 independent rANS streams for y (row bands)  */
@@ -67,13 +70,13 @@ typedef struct {
                                /* 0: device buffers plus async copies (Sec. III.D)   */
     int32_t  max_in_flight;    /* frames in flight = pooled slots per pipeline       */
     int32_t  max_h, max_w;     /* largest frame the pools are sized for              */
-    int32_t  max_batch;        /* frames per GPU launch (1 = per-frame)              */
+    int32_t  max_batch;        /* frames per task = per GPU launch (1..8)            */
     uint64_t hbm_budget_bytes; /* device memory the pools may take (0 = no limit)    */
     int32_t  hip_device;       /* HIP device ordinal                                 */
 } codec_config;
 
 /* Defaults: hyperprior, N=128, M=192, FP32, exp output, S=8, 8 entropy
- * threads, zero_copy=0, 6 frames in flight, 1088x1920 max, batch 1. */
+ * threads, zero_copy=1, 6 frames in flight, 1088x1920 max, batch 1. */
 void codec_default_config(codec_config* cfg);
 
 /* Creates a codec from a "LICW" weight blob (see DESIGN notes: per-layer
@@ -124,6 +127,8 @@ const char* codec_last_error(const codec_t* c);
 /* follow from the 64-multiple padded size Hp x Wp (latents Hp/16 x Wp/16,   */
 /* hyper-latents Hp/64 x Wp/64).  All tensors are NHWC except images.        */
 /*                                                                          */
+/*  In the BF16 form the NHWC activations in and out of GA0..GA2 and       */
+/*  GS0..GS2 (and into GA3 / GS3) are bf16; y, z, v and images stay f32.    */
 /*  layer          in                         out                aux         */
 /*  LIC_GA0..GA2   ga0: image NCHW f32         NHWC f32           -           */
 /*  LIC_GA3        NHWC f32                    y NHWC f32         sym_y int8  */

@@ -36,17 +36,18 @@ def _sync(*tensors):
 class Codec:
     """A codec instance: packed weights, tables, pools and pipeline threads."""
 
-    def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1,
-                 y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 0, max_in_flight: int = 6,
-                 max_h: int = 1088, max_w: int = 1920, hbm_budget_bytes: int = 0, device: int = 0):
+    def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1, precision: int = 0,
+                 y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 1, max_in_flight: int = 6,
+                 max_h: int = 1088, max_w: int = 1920, max_batch: int = 1, hbm_budget_bytes: int = 0,
+                 device: int = 0):
         cfg = _lib.CodecConfig()
         lib.codec_default_config(ctypes.byref(cfg))
-        cfg.kind, cfg.N, cfg.M, cfg.hs_out = kind, N, M, hs_out
+        cfg.kind, cfg.N, cfg.M, cfg.hs_out, cfg.precision = kind, N, M, hs_out, precision
         cfg.y_slices, cfg.entropy_threads, cfg.zero_copy = y_slices, entropy_threads, zero_copy
-        cfg.max_in_flight, cfg.max_h, cfg.max_w = max_in_flight, max_h, max_w
+        cfg.max_in_flight, cfg.max_h, cfg.max_w, cfg.max_batch = max_in_flight, max_h, max_w, max_batch
         cfg.hbm_budget_bytes, cfg.hip_device = hbm_budget_bytes, device
         self.cfg = cfg
-        self.kind, self.N, self.M, self.S = kind, N, M, y_slices
+        self.kind, self.N, self.M, self.S, self.precision = kind, N, M, y_slices, precision
         self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
         h = ctypes.c_void_p()
         rc = lib.codec_create(ctypes.byref(cfg), self._blob, len(blob), ctypes.byref(h))

@@ -35,6 +35,20 @@ bool check_frame(Codec* c, int n, int H, int W, int* rc)
     return true;
 }
 
+// Groups frames [0, n) into tasks of up to max_batch consecutive frames.
+void make_tasks(Codec* c, lic::CallState& cs, const float* x, float* x_hat, size_t fsz)
+{
+    const int B = c->cfg.max_batch;
+    for (int f = 0; f < cs.n; f += B) {
+        lic::Task* t = new lic::Task();
+        t->first = f;
+        t->nb = std::min(B, cs.n - f);
+        t->x = x ? x + (size_t)f * fsz : nullptr;
+        t->xhat = x_hat ? x_hat + (size_t)f * fsz : nullptr;
+        cs.tasks.emplace_back(t);
+    }
+}
+
 }  // namespace
 
 extern "C" {
@@ -52,7 +66,7 @@ void codec_default_config(codec_config* cfg)
     cfg->gs_mode = 0;
     cfg->y_slices = 8;
     cfg->entropy_threads = 8;
-    cfg->zero_copy = 0;
+    cfg->zero_copy = 1;
     cfg->max_in_flight = 6;
     cfg->max_h = 1088;
     cfg->max_w = 1920;
@@ -67,14 +81,14 @@ int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, cod
     if (!cfg || !blob || !out) { g_create_error = "null argument"; return LIC_E_ARG; }
     if (cfg->struct_size != sizeof(codec_config)) { g_create_error = "codec_config size mismatch"; return LIC_E_ARG; }
     if (!supported_shape(cfg->kind, cfg->N, cfg->M)) { g_create_error = "unsupported kind/N/M"; return LIC_E_ARG; }
-    if (cfg->precision != LIC_PREC_FP32) { g_create_error = "unsupported precision"; return LIC_E_ARG; }
+    if (cfg->precision != LIC_PREC_FP32 && cfg->precision != LIC_PREC_BF16) { g_create_error = "unsupported precision"; return LIC_E_ARG; }
     if (cfg->hs_out != LIC_HS_EXP && cfg->hs_out != LIC_HS_RELU) { g_create_error = "bad hs_out"; return LIC_E_ARG; }
     if (cfg->gs_mode != 0) { g_create_error = "unsupported gs_mode"; return LIC_E_ARG; }
     if (cfg->y_slices < 1 || cfg->y_slices > lic::kMaxSlices) { g_create_error = "y_slices must be 1..64"; return LIC_E_ARG; }
     if (cfg->entropy_threads < 1 || cfg->entropy_threads > 256) { g_create_error = "bad entropy_threads"; return LIC_E_ARG; }
     if (cfg->max_in_flight < 1 || cfg->max_in_flight > 64) { g_create_error = "max_in_flight must be 1..64"; return LIC_E_ARG; }
     if (cfg->max_h < 1 || cfg->max_w < 1 || cfg->max_h > 8192 || cfg->max_w > 8192) { g_create_error = "bad max_h/max_w"; return LIC_E_ARG; }
-    if (cfg->max_batch != 1) { g_create_error = "max_batch must be 1"; return LIC_E_ARG; }
+    if (cfg->max_batch < 1 || cfg->max_batch > lic::kMaxBatch) { g_create_error = "max_batch must be 1..8"; return LIC_E_ARG; }
     codec* c = new (std::nothrow) codec();
     if (!c) { g_create_error = "out of memory"; return LIC_E_NOMEM; }
     c->cfg = *cfg;
@@ -109,12 +123,7 @@ int codec_encode(codec_t* c, const float* x, int n, int H, int W, int is_device,
     cs.out = out;
     cs.cap = out ? cap : 0;
     cs.lens = lens;
-    const size_t fsz = (size_t)3 * H * W;
-    for (int i = 0; i < n; ++i) {
-        cs.tasks.emplace_back(new lic::Task());
-        cs.tasks[i]->frame = i;
-        cs.tasks[i]->x = x + i * fsz;
-    }
+    make_tasks(c, cs, x, nullptr, (size_t)3 * H * W);
     rc = c->run_call(cs);
     if (rc != LIC_OK) return rc;
     if (cs.overflow) return fail(c, LIC_E_SMALLBUF, "output capacity too small");
@@ -123,34 +132,29 @@ int codec_encode(codec_t* c, const float* x, int n, int H, int W, int is_device,
 
 namespace {
 
-int parse_all(Codec* c, const uint8_t* bits, const size_t* lens, int n, lic::CallState& cs, int* H, int* W)
+int parse_all(Codec* c, const uint8_t* bits, const size_t* lens, int n, lic::CallState& cs,
+              std::vector<lic::StreamHeader>* hdrs, std::vector<const uint8_t*>* zp, std::vector<size_t>* zl,
+              std::vector<std::vector<const uint8_t*>>* yp, std::vector<std::vector<size_t>>* yl)
 {
     size_t off = 0;
-    int h0 = -1, w0 = -1, s0 = -1;
+    hdrs->resize(n);
+    zp->resize(n);
+    zl->resize(n);
+    yp->resize(n);
+    yl->resize(n);
     for (int i = 0; i < n; ++i) {
-        lic::StreamHeader h;
-        const uint8_t* z;
-        size_t zl;
-        std::vector<const uint8_t*> yp;
-        std::vector<size_t> yl;
+        lic::StreamHeader& h = (*hdrs)[i];
         std::string e;
-        if (!lic::parse_stream(bits + off, lens[i], &h, &z, &zl, &yp, &yl, &e)) return fail(c, LIC_E_CORRUPT, e);
+        if (!lic::parse_stream(bits + off, lens[i], &h, &(*zp)[i], &(*zl)[i], &(*yp)[i], &(*yl)[i], &e))
+            return fail(c, LIC_E_CORRUPT, e);
         if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id)
             return fail(c, LIC_E_MODEL, "bitstream was produced by another model");
         if (h.S > lic::kMaxSlices) return fail(c, LIC_E_CORRUPT, "too many slices");
-        if (i == 0) { h0 = h.H; w0 = h.W; s0 = h.S; }
-        if (h.H != h0 || h.W != w0 || h.S != s0) return fail(c, LIC_E_ARG, "frames of one call must share size and slices");
-        lic::Task* t = new lic::Task();
-        cs.tasks.emplace_back(t);
-        t->frame = i;
-        t->zp = z;
-        t->zlen = zl;
-        for (int s = 0; s < h.S; ++s) { t->yp[s] = yp[s]; t->ylen[s] = yl[s]; }
+        if (h.H != (*hdrs)[0].H || h.W != (*hdrs)[0].W || h.S != (*hdrs)[0].S)
+            return fail(c, LIC_E_ARG, "frames of one call must share size and slices");
         off += lens[i];
     }
-    *H = h0;
-    *W = w0;
-    cs.S = s0 < 0 ? c->S : s0;
+    cs.S = (*hdrs)[0].S;
     return LIC_OK;
 }
 
@@ -164,9 +168,14 @@ int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n, flo
     if (n == 0) return LIC_OK;
     if (!bits || !lens || !x_hat || !H || !W) return fail(c, LIC_E_ARG, "null buffer");
     lic::CallState cs;
-    int h, w;
-    int rc = parse_all(c, bits, lens, n, cs, &h, &w);
+    std::vector<lic::StreamHeader> hdrs;
+    std::vector<const uint8_t*> zp;
+    std::vector<size_t> zl;
+    std::vector<std::vector<const uint8_t*>> yp;
+    std::vector<std::vector<size_t>> yl;
+    int rc = parse_all(c, bits, lens, n, cs, &hdrs, &zp, &zl, &yp, &yl);
     if (rc != LIC_OK) return rc;
+    const int h = hdrs[0].H, w = hdrs[0].W;
     if (!check_frame(c, n, h, w, &rc)) return rc;
     *H = h;
     *W = w;
@@ -179,7 +188,17 @@ int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n, flo
         cs.stages = {lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     else
         cs.stages = {lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
-    for (int i = 0; i < n; ++i) cs.tasks[i]->xhat = x_hat + i * fsz;
+    make_tasks(c, cs, nullptr, x_hat, fsz);
+    for (auto& t : cs.tasks)
+        for (int b = 0; b < t->nb; ++b) {
+            const int f = t->first + b;
+            t->zp[b] = zp[f];
+            t->zlen[b] = zl[f];
+            for (int s = 0; s < cs.S; ++s) {
+                t->yp[b][s] = yp[f][s];
+                t->ylen[b][s] = yl[f][s];
+            }
+        }
     return c->run_call(cs);
 }
 
@@ -202,13 +221,7 @@ int codec_encode_decode(codec_t* c, const float* x, int n, int H, int W, int is_
     cs.out = bits;
     cs.cap = bits ? cap : 0;
     cs.lens = lens;
-    const size_t fsz = (size_t)3 * H * W;
-    for (int i = 0; i < n; ++i) {
-        cs.tasks.emplace_back(new lic::Task());
-        cs.tasks[i]->frame = i;
-        cs.tasks[i]->x = x + i * fsz;
-        cs.tasks[i]->xhat = x_hat + i * fsz;
-    }
+    make_tasks(c, cs, x, x_hat, (size_t)3 * H * W);
     rc = c->run_call(cs);
     if (rc != LIC_OK) return rc;
     if (cs.overflow) return fail(c, LIC_E_SMALLBUF, "output capacity too small");

@@ -24,7 +24,7 @@ namespace lic {
 // ------------------------------------------------------------------ model
 struct LayerGPU {
     bool present = false;
-    int ld = 0, ep = 0;
+    int ld = 0, ep = 0, dt = 0;
     int cin = 0, co = 0, cop = 0;
     int k = 5;
     bool deconv = false;
@@ -32,7 +32,7 @@ struct LayerGPU {
     int nphase = 1;
     std::vector<PhaseDesc> host_ph;
     PhaseDesc* d_ph = nullptr;
-    float* d_w = nullptr;
+    uint8_t* d_w = nullptr;            // packed weights (float or bf16)
     float* d_bias = nullptr;
     float* d_gamma = nullptr;
     float* d_beta = nullptr;
@@ -56,42 +56,56 @@ struct FrameDims {
 struct Codec;
 
 constexpr int kMaxSlices = 64;
+constexpr int kMaxBatch = 8;
 
-// Per-frame task: the state machine that travels through the stage queues.
+// A task: up to max_batch consecutive frames of one call that travel
+// together through the stage queues (the state machine of the pipeline).
+// GPU stages launch every layer once for the whole batch; CPU stages split
+// it into per-frame, per-stream jobs.
 struct Task {
-    int frame = 0;
+    int index = 0;                     // position of the task in the call
+    int first = 0;                     // index of the first frame in the call
+    int nb = 1;                        // frames in this task
     int slot = -1;
-    int stage = 0;                     // index into the pipeline's stage list
-    const float* x = nullptr;          // input frame (caller memory)
-    float* xhat = nullptr;             // output frame (caller memory)
-    const uint8_t* bits_in = nullptr;  // decode input
-    size_t bits_in_len = 0;
+    int stage = -1;                    // index into the call's stage list
+    const float* x = nullptr;          // first input frame (frames are contiguous)
+    float* xhat = nullptr;             // first output frame
     std::atomic<int> jobs_left{0};
-    int status = 0;
+    std::atomic<int> status{0};
+    std::mutex err_m;
     std::string err;
     double t_admit = 0.0, t_done = 0.0;
-    size_t bits_len = 0;               // encoded length (in the slot buffer)
-    // encoder: lengths of the z stream (part 0 for the hyperprior) and y slices
-    size_t part_len[kMaxSlices + 1] = {};
-    // decoder: payload spans of the parsed bitstream
-    const uint8_t* zp = nullptr;
-    size_t zlen = 0;
-    const uint8_t* yp[kMaxSlices] = {};
-    size_t ylen[kMaxSlices] = {};
+    size_t bits_len[kMaxBatch] = {};
+    // encoder: stream lengths (z = part 0 for the hyperprior, then y slices)
+    size_t part_len[kMaxBatch][kMaxSlices + 1] = {};
+    // decoder: payload spans of each parsed bitstream
+    const uint8_t* zp[kMaxBatch] = {};
+    size_t zlen[kMaxBatch] = {};
+    const uint8_t* yp[kMaxBatch][kMaxSlices] = {};
+    size_t ylen[kMaxBatch][kMaxSlices] = {};
+
+    void fail(int code, const std::string& msg)
+    {
+        std::lock_guard<std::mutex> g(err_m);
+        if (status.load() == 0) {
+            err = msg;
+            status.store(code);
+        }
+    }
 };
 
-// Pooled per-frame buffers.  Host buffers are pinned (and mapped into the
-// device address space for zero-copy stores from the epilogues).
+// Pooled buffers of one task (max_batch frames).  Host buffers are pinned
+// and mapped into the device address space, so the epilogues can store
+// symbols and indices straight into them (zero-copy) or a DMA copy can.
 struct Slot {
-    int8_t* h_sym_y = nullptr;   int8_t* d_sym_y = nullptr;    // [Hy][Wy][M]
-    int8_t* h_sym_z = nullptr;   int8_t* d_sym_z = nullptr;    // [Hz][Wz][N]
-    uint8_t* h_idx = nullptr;    uint8_t* d_idx = nullptr;     // [Hy][Wy][M]
-    int8_t* dm_sym_y = nullptr;  int8_t* dm_sym_z = nullptr;   // device views of the pinned buffers
-    uint8_t* dm_idx = nullptr;
-    uint8_t* h_scratch = nullptr; size_t scratch_cap = 0;     // per-slice rANS output regions
-    uint8_t* h_bits = nullptr;    size_t bits_cap = 0;         // assembled bitstream
-    float* d_x = nullptr;                                      // input staging (host input)
-    float* d_xhat = nullptr;                                   // output staging (host output)
+    int8_t* h_sym_y = nullptr;   int8_t* d_sym_y = nullptr;    // [B][Hy][Wy][M]
+    int8_t* h_sym_z = nullptr;   int8_t* d_sym_z = nullptr;    // [B][Hz][Wz][N]
+    uint8_t* h_idx = nullptr;    uint8_t* d_idx = nullptr;     // [B][Hy][Wy][M]
+    int8_t* dm_sym_y = nullptr;  uint8_t* dm_idx = nullptr;    // device views of the pinned buffers
+    uint8_t* h_scratch = nullptr; size_t scratch_per_frame = 0; // per-stream rANS output regions
+    uint8_t* h_bits = nullptr;    size_t bits_per_frame = 0;    // assembled bitstreams
+    float* d_x = nullptr;                                       // input staging (host input)
+    float* d_xhat = nullptr;                                    // output staging (host output)
 };
 
 // Device scratch of one GPU stage (reused frame after frame in stream order).
@@ -161,7 +175,7 @@ private:
 };
 
 struct CallState {
-    int n = 0;
+    int n = 0;                     // frames
     int S = 1;                     // y slices of every frame in the call
     FrameDims dims;
     int is_device = 0;
@@ -170,8 +184,8 @@ struct CallState {
     // in-order sink
     std::mutex m;
     std::condition_variable cv;
-    int next_sink = 0;
-    int done = 0;
+    int next_sink = 0;             // next task to deliver
+    int done = 0;                  // delivered tasks
     std::vector<char> finished;
     uint8_t* out = nullptr;        // encoded output (packed back to back)
     size_t cap = 0;
@@ -250,8 +264,8 @@ struct Codec {
     int gpu_encode(Task* t, GpuStage& g);
     int gpu_hs(Task* t, GpuStage& g);
     int gpu_gs(Task* t, GpuStage& g);
-    int cpu_job(Task* t, int part);
-    int cpu_parts(StageKind k) const;
+    int cpu_job(Task* t, int frame, int part);
+    int cpu_parts(StageKind k) const;          // jobs per frame
     int cpu_finalize(Task* t, StageKind k);
     // allocation helpers (create time only)
     void* dev_alloc(size_t bytes);

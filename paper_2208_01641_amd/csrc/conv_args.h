@@ -24,6 +24,12 @@ enum Epilogue : int {
                      // out = clamp(v, 0, 1) cropped NCHW, aux = v padded NCHW
 };
 
+// Operand precision of a layer's GEMM.
+enum DType : int {
+    DT_F32 = 0,
+    DT_BF16 = 1,
+};
+
 // One phase of a layer.  A plain convolution has one phase; a stride-2
 // transposed convolution is split into the four sub-pixel phases, each a
 // stride-1 convolution over the input grid with its own subset of taps.
@@ -31,7 +37,7 @@ struct PhaseDesc {
     int32_t ntaps;
     int32_t oy, ox;          // output position = s_out * grid + (oy, ox)
     int32_t pad_;
-    const float* w;          // packed weights [ntaps][CoP][CIN] (device)
+    const void* w;           // packed weights [ntaps][CoP][CIN] (device, float or bf16)
     int8_t dy[32], dx[32];   // tap offsets: input = s_in * grid + (dy, dx)
 };
 

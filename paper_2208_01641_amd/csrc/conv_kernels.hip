@@ -1,4 +1,5 @@
-// Implicit-GEMM convolution kernels for CDNA4 (gfx950), FP32 on MFMA.
+// Implicit-GEMM convolution kernels for CDNA4 (gfx950) on MFMA: FP32
+// operands, or bf16 operands with FP32 accumulation (precision form).
 //
 // One kernel template covers every layer of the analysis / synthesis and
 // hyper transforms (strided 5x5 and 3x3 convolutions, and stride-2 5x5
@@ -29,11 +30,30 @@
 namespace lic {
 
 typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
 {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
+
+// Operand precision of the convolution GEMM (accumulation is always FP32).
+//   DT_F32 : v_mfma_f32_16x16x4_f32, 16-channel K chunks, 4 channels per lane
+//   DT_BF16: v_mfma_f32_16x16x32_bf16, 32-channel K chunks, 8 channels per
+//            lane (one 16-byte load); activations between layers are stored
+//            as bf16, GDN / IGDN and all epilogue arithmetic stay FP32.
+template <int DT> struct Prec;
+template <> struct Prec<DT_F32> {
+    using Frag = f4;
+    using Elem = float;
+    static constexpr int KCH = 16, KE = 4;
+};
+template <> struct Prec<DT_BF16> {
+    using Frag = bf16x8;
+    using Elem = __bf16;
+    static constexpr int KCH = 32, KE = 8;
+};
 
 // Blocks are dispatched round-robin over the 8 XCDs (block L goes to XCD
 // L % 8).  Give each XCD a contiguous range of logical tiles so that tiles
@@ -48,11 +68,22 @@ __device__ __forceinline__ int xcd_logical_tile(int L, int T)
 
 // TAG is the layer id: it changes no code but gives every layer its own
 // kernel symbol, so profiles attribute time per layer.
-template <int TAG, int CIN, int MT, int NT, int WAVES, int LD, int EP>
-__global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
+// KSPLIT > 1 (small grids): the WAVES = KSPLIT waves of a block share one
+// output tile and take interleaved K chunks; their partial sums are added in
+// LDS in the fixed wave order 0, 1, ..., KSPLIT-1, so results do not depend
+// on timing, batch size or which stream runs the kernel.
+template <int TAG, int CIN, int MT, int NT, int WAVES, int KSPLIT, int LD, int EP, int DT>
+__global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 {
-    constexpr int KC = CIN / 16;
-    static_assert(CIN % 16 == 0, "K chunks of 16");
+    using Frag = typename Prec<DT>::Frag;
+    using Elem = typename Prec<DT>::Elem;
+    constexpr int KCH = Prec<DT>::KCH, KE = Prec<DT>::KE;
+    constexpr int KC = CIN / KCH;
+    static_assert(CIN % KCH == 0, "whole K chunks");
+    static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
+    static_assert(KSPLIT == 1 || KSPLIT == WAVES, "split-K blocks share one tile");
+    static_assert(KSPLIT == 1 || EP != EP_RGB, "no split-K for the RGB output layer");
+    constexpr int PIXW = WAVES / KSPLIT;           // waves with distinct pixel groups
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int l16 = lane & 15;
@@ -65,14 +96,17 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
     const int tile = logical / a.nphase;
     const PhaseDesc* __restrict__ ph = a.ph + phase;
     const int ntaps = ph->ntaps;
-    const float* __restrict__ wbase = ph->w;
+    const Elem* __restrict__ wbase = static_cast<const Elem*>(ph->w);
     const int CoP = a.ncog * MT * 16;
     const int co0 = cog * MT * 16;
 
     const int HWg = a.Hg * a.Wg;
     const int total = a.n * HWg;
-    const int pix0 = (tile * WAVES + wave) * (NT * 16);
-    if (pix0 >= total) return;   // no LDS, no barriers: whole idle waves may leave
+    const int kslot = wave % KSPLIT;
+    const int pix0 = (tile * PIXW + wave / KSPLIT) * (NT * 16);
+    // without split-K there is no barrier, so idle waves may leave; with it,
+    // every wave of the block has the same pix0 and leaves together
+    if (pix0 >= total) return;
 
     int img[NT], gy[NT], gx[NT];
     bool pv[NT];
@@ -90,34 +124,35 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
     f4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
-        const f4 b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
+        f4 b = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (kslot == 0) b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = b;
     }
 
-    auto loadA = [&](int t, int kc, f4 (&A)[MT]) {
-        const float* wp = wbase + ((long)t * CoP + co0 + l16) * CIN + kc * 16 + kg * 4;
+    auto loadA = [&](int t, int kc, Frag (&A)[MT]) {
+        const Elem* wp = wbase + ((long)t * CoP + co0 + l16) * CIN + kc * KCH + kg * KE;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const f4*>(wp + (long)mt * 16 * CIN);
+        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
     };
 
-    auto loadB = [&](int t, int kc, f4 (&B)[NT]) {
+    auto loadB = [&](int t, int kc, Frag (&B)[NT]) {
         if constexpr (LD == LD_RGB) {
             // 5x5 stride-2 taps over 3 channels flattened: k = (5u + v) * 3 + c, zero beyond 75.
             const float* in = static_cast<const float*>(a.in);
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                f4 v;
+                Frag v;
 #pragma unroll
-                for (int e = 0; e < 4; ++e) {
-                    const int k = kc * 16 + kg * 4 + e;
+                for (int e = 0; e < KE; ++e) {
+                    const int k = kc * KCH + kg * KE + e;
                     const int tap = k / 3, c = k - 3 * (k / 3);
                     const int u = tap / 5, w = tap - 5 * (tap / 5);
                     const int iy = gy[nt] * 2 + u - 2, ix = gx[nt] * 2 + w - 2;
                     const bool ok = pv[nt] && k < 75 && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
                     float val = 0.0f;
                     if (ok) val = in[(((long)img[nt] * 3 + c) * a.Hin + iy) * a.Win + ix];
-                    v[e] = val;
+                    v[e] = (Elem)val;
                 }
                 B[nt] = v;
             }
@@ -127,19 +162,28 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
             for (int nt = 0; nt < NT; ++nt) {
                 const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
                 const bool ok = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-                const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kc * 16 + kg * 4;
-                f4 v = {0.0f, 0.0f, 0.0f, 0.0f};
+                const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kc * KCH + kg * KE;
+                Frag v = {};
                 if constexpr (LD == LD_I8) {
+                    // y_hat / z_hat = symbol + per-channel offset; zero outside the image
                     if (ok) {
-                        const uint32_t u = *reinterpret_cast<const uint32_t*>(static_cast<const int8_t*>(a.in) + off);
-                        const f4 mu = *reinterpret_cast<const f4*>(a.mu_in + kc * 16 + kg * 4);
-                        v[0] = (float)(int8_t)(u & 0xffu) + mu[0];
-                        v[1] = (float)(int8_t)((u >> 8) & 0xffu) + mu[1];
-                        v[2] = (float)(int8_t)((u >> 16) & 0xffu) + mu[2];
-                        v[3] = (float)(int8_t)(u >> 24) + mu[3];
+                        const int8_t* src = static_cast<const int8_t*>(a.in) + off;
+                        const float* mu = a.mu_in + kc * KCH + kg * KE;
+                        if constexpr (KE == 4) {
+                            const uint32_t u = *reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) v[e] = (Elem)((float)(int8_t)(u >> (8 * e)) + mu[e]);
+                        } else {
+                            const uint2 u = *reinterpret_cast<const uint2*>(src);
+#pragma unroll
+                            for (int e = 0; e < 4; ++e) {
+                                v[e] = (Elem)((float)(int8_t)(u.x >> (8 * e)) + mu[e]);
+                                v[4 + e] = (Elem)((float)(int8_t)(u.y >> (8 * e)) + mu[4 + e]);
+                            }
+                        }
                     }
                 } else {
-                    if (ok) v = *reinterpret_cast<const f4*>(static_cast<const float*>(a.in) + off);
+                    if (ok) v = *reinterpret_cast<const Frag*>(static_cast<const Elem*>(a.in) + off);
                     if constexpr (LD == LD_F32_ABS) {
                         v[0] = fabsf(v[0]); v[1] = fabsf(v[1]); v[2] = fabsf(v[2]); v[3] = fabsf(v[3]);
                     }
@@ -149,33 +193,79 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
         }
     };
 
-    auto compute = [&](const f4 (&A)[MT], const f4 (&B)[NT]) {
+    auto compute = [&](const Frag (&A)[MT], const Frag (&B)[NT]) {
+        if constexpr (DT == DT_F32) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
+            for (int e = 0; e < 4; ++e)
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], B[nt][e], acc[mt][nt]);
+        } else {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], B[nt][e], acc[mt][nt]);
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+        }
     };
 
-    // K loop, double-buffered in registers: chunk k+1 is in flight while
-    // chunk k feeds the matrix cores.
+    // stores 4 consecutive channels of one pixel in the activation storage type
+    auto store_act = [&](long idx, const f4& y) {
+        if constexpr (DT == DT_F32) {
+            *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
+        } else {
+            bf16x4 h;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) h[i] = (__bf16)y[i];
+            *reinterpret_cast<bf16x4*>(static_cast<__bf16*>(a.out) + idx) = h;
+        }
+    };
+
+    // K loop over this wave's chunks k = kslot, kslot + KSPLIT, ..., with a
+    // register ring of P chunk buffers: P - 1 chunks are in flight while one
+    // feeds the matrix cores (deeper for small tiles, which have less MFMA
+    // work per chunk to hide the load latency behind).
+    constexpr int P = (MT * NT <= 2) ? 4 : 2;
     const int K = ntaps * KC;
-    f4 A0[MT], B0[NT], A1[MT], B1[NT];
-    loadA(0, 0, A0);
-    loadB(0, 0, B0);
-    for (int k = 0; k < K; k += 2) {
-        const bool has1 = k + 1 < K;
-        if (has1) {
-            loadA((k + 1) / KC, (k + 1) % KC, A1);
-            loadB((k + 1) / KC, (k + 1) % KC, B1);
+    const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
+    Frag Ab[P][MT], Bb[P][NT];
+#pragma unroll
+    for (int j = 0; j < P - 1; ++j)
+        if (j < nk) {
+            const int kk = kslot + j * KSPLIT;
+            loadA(kk / KC, kk % KC, Ab[j]);
+            loadB(kk / KC, kk % KC, Bb[j]);
         }
-        compute(A0, B0);
-        if (k + 2 < K) {
-            loadA((k + 2) / KC, (k + 2) % KC, A0);
-            loadB((k + 2) / KC, (k + 2) % KC, B0);
+    for (int k0 = 0; k0 < nk; k0 += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            const int k = k0 + j;
+            if (k >= nk) break;
+            if (k + P - 1 < nk) {
+                const int kk = kslot + (k + P - 1) * KSPLIT;
+                loadA(kk / KC, kk % KC, Ab[(j + P - 1) % P]);
+                loadB(kk / KC, kk % KC, Bb[(j + P - 1) % P]);
+            }
+            compute(Ab[j], Bb[j]);
         }
-        if (has1) compute(A1, B1);
+    }
+
+    if constexpr (KSPLIT > 1) {
+        __shared__ f4 red[(KSPLIT > 1 ? KSPLIT - 1 : 1) * MT * NT * 64];
+        if (kslot > 0) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) red[(((kslot - 1) * MT + mt) * NT + nt) * 64 + lane] = acc[mt][nt];
+        }
+        __syncthreads();
+        if (kslot > 0) return;
+        for (int w = 1; w < KSPLIT; ++w)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] += red[(((w - 1) * MT + mt) * NT + nt) * 64 + lane];
     }
 
     // ------------------------------------------------------------ epilogue
@@ -213,7 +303,6 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) nacc[mt][nt] = mfma16x16x4(G[mt][e], X[nt][e], nacc[mt][nt]);
         }
-        float* out = static_cast<float*>(a.out);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -224,10 +313,9 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
                     const float r = sqrtf(nacc[mt][nt][i]);
                     y[i] = (EP == EP_GDN) ? acc[mt][nt][i] / r : acc[mt][nt][i] * r;
                 }
-                if (pv[nt]) *reinterpret_cast<f4*>(out + obase[nt] + mt * 16 + kg * 4) = y;
+                if (pv[nt]) store_act(obase[nt] + mt * 16 + kg * 4, y);
             }
     } else if constexpr (EP == EP_NONE || EP == EP_RELU) {
-        float* out = static_cast<float*>(a.out);
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
@@ -238,7 +326,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm_f32(ConvArgs a)
 #pragma unroll
                     for (int i = 0; i < 4; ++i) y[i] = fmaxf(y[i], 0.0f);
                 }
-                if (pv[nt] && c < a.Co) *reinterpret_cast<f4*>(out + obase[nt] + c) = y;
+                if (pv[nt] && c < a.Co) store_act(obase[nt] + c, y);
             }
     } else if constexpr (EP == EP_QUANT) {
         float* out = static_cast<float*>(a.out);
@@ -321,17 +409,33 @@ struct KernelEntry {
     void (*fn)(ConvArgs);
 };
 
-#define LIC_K(TAG, CIN, MT, NT, WV, LD, EP) \
-    {{TAG, CIN, MT, NT, WV, LD, EP}, conv_igemm_f32<TAG, CIN, MT, NT, WV, LD, EP>}
-// both tile configurations of a non-GDN layer: large (4 m-tiles x 2 n-tiles,
-// 4 waves) and small (1 x 1, one wave) for grids too small to fill the chip
-#define LIC_K2(TAG, CIN, LD, EP) LIC_K(TAG, CIN, 4, 2, 4, LD, EP), LIC_K(TAG, CIN, 1, 1, 1, LD, EP)
+#define LIC_KSD(TAG, CIN, MT, NT, WV, KS, LD, EP, DT) \
+    {{TAG, CIN, MT, NT, WV, KS, LD, EP, DT}, conv_igemm<TAG, CIN, MT, NT, WV, KS, LD, EP, DT>}
+#define LIC_KS(TAG, CIN, MT, NT, WV, KS, LD, EP) LIC_KSD(TAG, CIN, MT, NT, WV, KS, LD, EP, DT_F32)
+#define LIC_K(TAG, CIN, MT, NT, WV, LD, EP) LIC_KS(TAG, CIN, MT, NT, WV, 1, LD, EP)
+// bf16 operand variants of the analysis / synthesis layers
+#define LIC_KB(TAG, CIN, MT, NT, WV, LD, EP) LIC_KSD(TAG, CIN, MT, NT, WV, 1, LD, EP, DT_BF16)
+#define LIC_KGB(TAG, CIN, MT, NT, LD, EP) \
+    LIC_KSD(TAG, CIN, MT, NT, 4, 1, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, MT, NT, 4, 4, LD, EP, DT_BF16)
+#define LIC_K2B(TAG, CIN, LD, EP)                                                                \
+    LIC_KSD(TAG, CIN, 4, 2, 4, 1, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 4, 2, 4, 4, LD, EP, DT_BF16), \
+        LIC_KSD(TAG, CIN, 4, 2, 8, 8, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 1, 1, 8, 8, LD, EP, DT_BF16)
+// the tile configurations of a non-GDN layer: large (4 m-tiles x 2 n-tiles,
+// 4 pixel-parallel waves), large with 4-way split-K, and small (1 x 1) with
+// 8-way split-K, for grids too small to fill the chip
+// GDN / IGDN layers: pixel-parallel, or 4-way split-K with the
+// normalisation done by the first wave after the reduction
+#define LIC_KG(TAG, CIN, MT, NT, LD, EP) LIC_K(TAG, CIN, MT, NT, 4, LD, EP), LIC_KS(TAG, CIN, MT, NT, 4, 4, LD, EP)
+#define LIC_K2(TAG, CIN, LD, EP)                                                               \
+    LIC_K(TAG, CIN, 4, 2, 4, LD, EP), LIC_KS(TAG, CIN, 4, 2, 4, 4, LD, EP), LIC_KS(TAG, CIN, 4, 2, 8, 8, LD, EP), \
+        LIC_KS(TAG, CIN, 1, 1, 8, 8, LD, EP)
 
 static const KernelEntry kEntries[] = {
-    // g_a: GDN layers hold every channel of their pixels in one wave
+    // g_a: GDN layers hold every channel of their pixels in one wave (split-K
+    // variants for grids that would leave SIMDs idle)
     LIC_K(LIC_GA0, 80, 8, 2, 4, LD_RGB, EP_GDN), LIC_K(LIC_GA0, 80, 12, 1, 4, LD_RGB, EP_GDN),
-    LIC_K(LIC_GA1, 128, 8, 2, 4, LD_F32, EP_GDN), LIC_K(LIC_GA1, 192, 12, 1, 4, LD_F32, EP_GDN),
-    LIC_K(LIC_GA2, 128, 8, 2, 4, LD_F32, EP_GDN), LIC_K(LIC_GA2, 192, 12, 1, 4, LD_F32, EP_GDN),
+    LIC_KG(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KG(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_KG(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KG(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_K2(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2(LIC_GA3, 192, LD_F32, EP_QUANT),
     // h_a
     LIC_K2(LIC_HA0, 192, LD_F32_ABS, EP_RELU), LIC_K2(LIC_HA0, 320, LD_F32_ABS, EP_RELU),
@@ -342,10 +446,19 @@ static const KernelEntry kEntries[] = {
     LIC_K2(LIC_HS1, 128, LD_F32, EP_RELU), LIC_K2(LIC_HS1, 192, LD_F32, EP_RELU),
     LIC_K2(LIC_HS2, 128, LD_F32, EP_INDEX), LIC_K2(LIC_HS2, 192, LD_F32, EP_INDEX),
     // g_s
-    LIC_K(LIC_GS0, 192, 8, 2, 4, LD_I8, EP_IGDN), LIC_K(LIC_GS0, 320, 12, 1, 4, LD_I8, EP_IGDN),
-    LIC_K(LIC_GS1, 128, 8, 2, 4, LD_F32, EP_IGDN), LIC_K(LIC_GS1, 192, 12, 1, 4, LD_F32, EP_IGDN),
-    LIC_K(LIC_GS2, 128, 8, 2, 4, LD_F32, EP_IGDN), LIC_K(LIC_GS2, 192, 12, 1, 4, LD_F32, EP_IGDN),
+    LIC_KG(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KG(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
+    LIC_KG(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KG(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_K(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_K(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    // bf16 operands (precision form): g_a and g_s; h_a / h_s stay FP32
+    LIC_KB(LIC_GA0, 96, 8, 2, 4, LD_RGB, EP_GDN), LIC_KB(LIC_GA0, 96, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_KGB(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGB(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_KGB(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGB(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_K2B(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2B(LIC_GA3, 192, LD_F32, EP_QUANT),
+    LIC_KGB(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KGB(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
+    LIC_KGB(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
 };
 
 bool kernel_available(const KernelKey& k)

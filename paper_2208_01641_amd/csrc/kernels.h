@@ -10,11 +10,11 @@ namespace lic {
 // input channels per tap (K chunking), m-tiles (16 output channels each) and
 // n-tiles (16 pixels each) per wave, waves per block, loader and epilogue.
 struct KernelKey {
-    int tag, cin, mt, nt, waves, ld, ep;   // tag = layer id (one kernel symbol per layer)
+    int tag, cin, mt, nt, waves, ksplit, ld, ep, dt;   // tag = layer id (one kernel symbol per layer)
     bool operator==(const KernelKey& o) const
     {
-        return tag == o.tag && cin == o.cin && mt == o.mt && nt == o.nt && waves == o.waves && ld == o.ld &&
-               ep == o.ep;
+        return tag == o.tag && cin == o.cin && mt == o.mt && nt == o.nt && waves == o.waves &&
+               ksplit == o.ksplit && ld == o.ld && ep == o.ep && dt == o.dt;
     }
 };
 

@@ -93,6 +93,16 @@ bool parse_blob(const uint8_t* b, size_t len, int* kind, int* N, int* M, ParamMa
 
 }  // namespace
 
+// float32 -> bfloat16, round to nearest even (NaN stays NaN)
+uint16_t bf16_rne(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
 bool build_tables(const ParamMap& P, int kind, int N, int M, std::vector<float>* medians,
                   std::vector<uint32_t>* fact_freq, std::vector<uint32_t>* gauss_freq, std::string* err)
 {
@@ -237,7 +247,12 @@ int Codec::build_layers(const ParamMap& P)
         L.deconv = sp.deconv;
         L.co = co;
         L.rows = sp.ep == EP_RGB;
-        L.cin = sp.ld == LD_RGB ? 80 : ci;
+        // bf16 operands for the analysis / synthesis transforms in the BF16
+        // form; h_a and h_s always run in FP32 (fixed-order scale index)
+        const bool is_gags = sp.id <= LIC_GA3 || sp.id >= LIC_GS0;
+        L.dt = (cfg.precision == LIC_PREC_BF16 && is_gags) ? DT_BF16 : DT_F32;
+        const int krgb = L.dt == DT_BF16 ? 96 : 80;   // 75 (tap, channel) pairs in whole K chunks
+        L.cin = sp.ld == LD_RGB ? krgb : ci;
         L.cop = L.rows ? 16 : co;
         if (sp.ld == LD_RGB && ci != 3) { err = "ga0 must take 3 channels"; return LIC_E_MODEL; }
         if (!L.rows && co % 16 != 0) { err = std::string("channels must be multiples of 16: ") + sp.name; return LIC_E_MODEL; }
@@ -255,11 +270,11 @@ int Codec::build_layers(const ParamMap& P)
             PhaseDesc d{};
             d.ntaps = 1;
             ph.push_back(d);
-            std::vector<float> wp((size_t)L.cop * 80, 0.0f);
+            std::vector<float> wp((size_t)L.cop * krgb, 0.0f);
             for (int o = 0; o < co; ++o)
                 for (int u = 0; u < 5; ++u)
                     for (int v = 0; v < 5; ++v)
-                        for (int c = 0; c < 3; ++c) wp[(size_t)o * 80 + (u * 5 + v) * 3 + c] = (float)W(o, c, u, v);
+                        for (int c = 0; c < 3; ++c) wp[(size_t)o * krgb + (u * 5 + v) * 3 + c] = (float)W(o, c, u, v);
             packed.push_back(std::move(wp));
         } else if (!sp.deconv) {
             PhaseDesc d{};
@@ -328,14 +343,21 @@ int Codec::build_layers(const ParamMap& P)
 
         size_t total = 0;
         for (auto& v : packed) total += v.size();
-        L.d_w = (float*)dev_alloc(total * sizeof(float));
+        const size_t esz = L.dt == DT_BF16 ? 2 : 4;
+        L.d_w = (uint8_t*)dev_alloc(total * esz);
         L.d_ph = (PhaseDesc*)dev_alloc(ph.size() * sizeof(PhaseDesc));
         L.d_bias = (float*)dev_alloc(L.cop * sizeof(float));
         if (!L.d_w || !L.d_ph || !L.d_bias) { err = "device allocation failed"; return LIC_E_NOMEM; }
         size_t off = 0;
         for (size_t i = 0; i < packed.size(); ++i) {
-            HIP_TRY(hipMemcpy(L.d_w + off, packed[i].data(), packed[i].size() * sizeof(float), hipMemcpyHostToDevice));
-            ph[i].w = L.d_w + off;
+            if (L.dt == DT_BF16) {
+                std::vector<uint16_t> hb(packed[i].size());
+                for (size_t j = 0; j < hb.size(); ++j) hb[j] = bf16_rne(packed[i][j]);
+                HIP_TRY(hipMemcpy(L.d_w + off * esz, hb.data(), hb.size() * esz, hipMemcpyHostToDevice));
+            } else {
+                HIP_TRY(hipMemcpy(L.d_w + off * esz, packed[i].data(), packed[i].size() * esz, hipMemcpyHostToDevice));
+            }
+            ph[i].w = L.d_w + off * esz;
             off += packed[i].size();
         }
         HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
@@ -427,29 +449,43 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.Hc = d.H;
     a.Wc = d.W;
 
-    KernelKey key{id, L.cin, 0, 0, 0, L.ld, L.ep};
+    KernelKey key{id, L.cin, 0, 0, 0, 1, L.ld, L.ep, L.dt};
     const long pixels = (long)n * g.Hg * g.Wg;
     if (L.ep == EP_GDN || L.ep == EP_IGDN) {
         key.mt = L.co / 16;
         key.nt = key.mt <= 8 ? 2 : 1;
         key.waves = 4;
         a.ncog = 1;
+        // fewer than one wave per SIMD (1024 on the chip) from the pixel
+        // grid of one image: split K over the 4 waves of a block instead
+        const long img_waves = ((long)g.Hg * g.Wg + 16 * key.nt - 1) / (16 * key.nt) * L.nphase;
+        if (L.ld != LD_RGB && img_waves < 1024) key.ksplit = 4;
     } else if (L.ep == EP_RGB) {
         key.mt = 1;
         key.nt = 4;
         key.waves = 4;
         a.ncog = 1;
     } else {
-        // large tiles when they still give the chip >= 4 waves per CU
-        const long big_waves = ((pixels + 31) / 32) * L.nphase * (L.cop / 64);
-        if (L.cop % 64 == 0 && big_waves >= 1024) {
-            key.mt = 4; key.nt = 2; key.waves = 4;
+        // 64-channel x 32-pixel wave tiles; when the grid of one image gives
+        // fewer than 2 waves per SIMD, split K over 4 or 8 waves of a block;
+        // only the tiniest layers fall back to 16 x 16 tiles (split 8).  The
+        // choice depends on the per-image size only, so a frame gives the
+        // same bits alone or in a batch (split-K changes the summation order).
+        const long img_pixels = (long)g.Hg * g.Wg;
+        const long tiles_big = ((img_pixels + 31) / 32) * L.nphase * (L.cop / 64);
+        key.mt = 4; key.nt = 2;
+        if (L.cop % 64 != 0 || tiles_big < 32) {
+            key.mt = 1; key.nt = 1; key.waves = 8; key.ksplit = 8;
+        } else if (tiles_big >= 2048) {
+            key.waves = 4; key.ksplit = 1;
+        } else if (tiles_big * 4 >= 2048) {
+            key.waves = 4; key.ksplit = 4;
         } else {
-            key.mt = 1; key.nt = 1; key.waves = 1;
+            key.waves = 8; key.ksplit = 8;
         }
         a.ncog = L.cop / (16 * key.mt);
     }
-    const long per_block = (long)key.waves * key.nt * 16;
+    const long per_block = (long)(key.waves / key.ksplit) * key.nt * 16;
     const long tiles = (pixels + per_block - 1) / per_block;
     const long nblocks = tiles * L.nphase * a.ncog;
     if (nblocks <= 0) return LIC_OK;

@@ -165,6 +165,28 @@ def test_pipeline_many_frames_in_order(torch_dev):
     c.close()
 
 
+def test_batched_tasks_equal_per_frame(torch_dev):
+    """Frames coded in tasks of 3 (one launch per layer for 3 frames) give
+    the same bytes and pixels as frame-by-frame tasks."""
+    torch = torch_dev
+    H, W = 136, 264
+    c1, _ = make_codec(1, 128, 192, max_h=H, max_w=W, y_slices=3, entropy_threads=4, max_in_flight=3)
+    c3, _ = make_codec(1, 128, 192, max_h=H, max_w=W, y_slices=3, entropy_threads=4, max_in_flight=2, max_batch=3)
+    xs = torch.from_numpy(np.stack([synth.frame_sinusoid(H, W, t=t) for t in range(7)])).cuda()
+    b1 = c1.encode(xs)
+    b3 = c3.encode(xs)
+    assert b1 == b3
+    o1 = torch.empty((7, 3, H, W), device="cuda")
+    o3 = torch.empty_like(o1)
+    c1.decode(b1, o1)
+    c3.decode(b3, o3)
+    assert torch.equal(o1, o3)
+    o4 = torch.empty_like(o1)
+    assert c3.encode_decode(xs, o4) == b1 and torch.equal(o4, o1)
+    c1.close()
+    c3.close()
+
+
 def test_host_buffers_and_errors(torch_dev):
     from paper_2208_01641_amd import LicError
     torch = torch_dev

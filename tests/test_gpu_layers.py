@@ -163,4 +163,20 @@ def test_batched_layers_equal_single(torch_dev):
         o = _empty(torch, layer_out_shape("GA0", H, W, 128, 192))
         c.run_layer("GA0", 1, H, W, xd[i:i + 1].contiguous(), o)
         assert torch.equal(o[0], outb[i])
+    # split-K layers too: the tile configuration depends on the image size only
+    g = torch.Generator(device="cuda").manual_seed(3)
+    for L, src in (("GA3", "GA2"), ("HA1", "HA0"), ("HS2", "HS1")):
+        shp = layer_out_shape(src, H, W, 128, 192)
+        inp = torch.randn((3,) + shp, device="cuda", generator=g)
+        dt = torch.uint8 if L == "HS2" else torch.float32
+        ob = torch.empty((3,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=dt)
+        ab = torch.empty((3,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=torch.int8) if L == "GA3" else None
+        c.run_layer(L, 3, H, W, inp, ob, ab)
+        for i in range(3):
+            o1 = torch.empty_like(ob[:1])
+            a1 = torch.empty_like(ab[:1]) if ab is not None else None
+            c.run_layer(L, 1, H, W, inp[i:i + 1].contiguous(), o1, a1)
+            assert torch.equal(o1[0], ob[i]), L
+            if ab is not None:
+                assert torch.equal(a1[0], ab[i])
     c.close()
