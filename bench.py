@@ -13,7 +13,8 @@ The headline line is the FP32 form at N=128, M=192.  Unless --no-variants
 is given, the same JSON line also carries the comparison runs ("variants"):
 the unpipelined per-frame form (one frame in flight), the BF16 form at
 720p, and the FP32 / BF16 forms of the 1080p N=192 M=320 batch-4 workload,
-each with frames/s, p50/p99 latency, PSNR and bits per pixel.
+each with frames/s, p50/p99 latency, PSNR and bits per pixel, and the
+serving loop (16 mixed-resolution streams, Poisson arrivals, BF16).
 
 Prints one JSON line.
 """
@@ -150,6 +151,90 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
     return res, x0, P, blob
 
 
+def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7):
+    """16 concurrent streams (8 x 360p, 4 x 720p, 4 x 1080p), Poisson frame
+    arrivals at 30 fps per stream, served through submit/poll with
+    continuous batching (per-size buckets, batches of up to 4, captured HIP
+    graphs); every encoded frame is resubmitted for decoding.  Returns the
+    completed frames/s and the latency percentiles after the warm-up."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_01641_amd import Codec
+
+    N, M = 128, 192
+    sizes = [(360, 640)] * 8 + [(720, 1280)] * 4 + [(1080, 1920)] * 4
+    P = synth.model_params(1, N, M)
+    blob = synth.weight_blob(P, 1, N, M)
+    codec = Codec(blob, kind=1, N=N, M=M, hs_out=1, precision=precision, y_slices=4, entropy_threads=threads,
+                  zero_copy=1, max_in_flight=8, max_h=1080, max_w=1920, max_batch=4, use_graphs=1)
+    sids = [codec.open_stream(H, W) for H, W in sizes]
+    frames = [synth.frames_sinusoid_torch(H, W, range(4), stream=s, device="cuda") for s, (H, W) in enumerate(sizes)]
+    ring = 48
+    bits_buf = [[np.zeros(codec.max_stream_bytes(H, W), np.uint8) for _ in range(ring)] for H, W in sizes]
+    img_buf = [[torch.empty((3, H, W), device="cuda") for _ in range(ring)] for H, W in sizes]
+    rng = np.random.default_rng(seed)
+    total = warmup_s + duration_s
+    arrivals = []
+    for s in range(len(sizes)):
+        t = rng.exponential(1 / 30.0)
+        while t < total:
+            arrivals.append((t, s))
+            t += rng.exponential(1 / 30.0)
+    arrivals.sort()
+    torch.cuda.synchronize()
+    enc_of, dec_of, meta = {}, {}, {}
+    lat_enc, lat_dec, lat_e2e = [], [], []
+    done_frames = 0
+    nxt = 0
+    k = [0] * len(sizes)
+    t0 = time.perf_counter()
+    t_meas = None
+    outstanding = 0
+    while nxt < len(arrivals) or outstanding:
+        now = time.perf_counter() - t0
+        while nxt < len(arrivals) and arrivals[nxt][0] <= now:
+            ta, s = arrivals[nxt]
+            j = k[s] % ring
+            tk = codec.submit_encode(sids[s], frames[s][k[s] % 4], bits_buf[s][j])
+            enc_of[tk] = (s, j, ta)
+            k[s] += 1
+            nxt += 1
+            outstanding += 1
+        for r in codec.poll(256, 200):
+            if r["direction"] == 0:
+                s, j, ta = enc_of.pop(r["ticket"])
+                assert r["status"] == 0, r
+                arr = bits_buf[s][j][:r["bytes"]]
+                tk = codec.submit_decode(sids[s], arr, img_buf[s][j])
+                dec_of[tk] = (s, ta, r["latency_ms"])
+                if ta >= warmup_s:
+                    lat_enc.append(r["latency_ms"])
+            else:
+                s, ta, le = dec_of.pop(r["ticket"])
+                assert r["status"] == 0, r
+                outstanding -= 1
+                if ta >= warmup_s:
+                    lat_dec.append(r["latency_ms"])
+                    lat_e2e.append(1e3 * (time.perf_counter() - t0 - ta))
+                    done_frames += 1
+                    if t_meas is None:
+                        t_meas = time.perf_counter()
+        if nxt < len(arrivals) and not outstanding:
+            time.sleep(max(0.0, arrivals[nxt][0] - (time.perf_counter() - t0)))
+    t_end = time.perf_counter()
+    codec.close()
+    del frames, img_buf
+    torch.cuda.empty_cache()
+    pct = lambda a, q: float(np.percentile(a, q)) if a else None
+    return {"streams": len(sizes), "offered_fps": 30 * len(sizes), "frames": done_frames,
+            "fps": done_frames / (t_end - t_meas) if t_meas else 0.0,
+            "enc_p50_ms": pct(lat_enc, 50), "enc_p99_ms": pct(lat_enc, 99),
+            "dec_p50_ms": pct(lat_dec, 50), "dec_p99_ms": pct(lat_dec, 99),
+            "e2e_p50_ms": pct(lat_e2e, 50), "e2e_p99_ms": pct(lat_e2e, 99)}
+
+
 def _round(d, nd=3):
     return {k: (round(v, nd) if isinstance(v, float) else v) for k, v in d.items()}
 
@@ -248,6 +333,7 @@ def main():
             var[f"{name}_1080p_n192_m320_batch4"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
         var["bf16_1080p_n192_m320_batch4"]["d_psnr_db_vs_fp32"] = round(big["bf16"]["psnr_db"] - big["fp32"]["psnr_db"], 4)
         var["bf16_1080p_n192_m320_batch4"]["d_bpp_vs_fp32"] = round(big["bf16"]["bpp"] - big["fp32"]["bpp"], 5)
+        var["serving_16_streams_bf16"] = _round(run_serving(precision=1, threads=threads))
         res["variants"] = var
 
     if not args.no_cpu_baseline:

@@ -71,12 +71,15 @@ typedef struct {
     int32_t  max_in_flight;    /* frames in flight = pooled slots per pipeline       */
     int32_t  max_h, max_w;     /* largest frame the pools are sized for              */
     int32_t  max_batch;        /* frames per task = per GPU launch (1..8)            */
-    uint64_t hbm_budget_bytes; /* device memory the pools may take (0 = no limit)    */
+    uint64_t hbm_budget_bytes; /* device memory the codec may take: pools plus the   */
+                               /* reservations of open serving streams (0 = no limit)*/
     int32_t  hip_device;       /* HIP device ordinal                                 */
+    int32_t  use_graphs;       /* serving: run each GPU stage of a (frame size,      */
+                               /* batch, slot) as a captured HIP graph               */
 } codec_config;
 
 /* Defaults: hyperprior, N=128, M=192, FP32, exp output, S=8, 8 entropy
- * threads, zero_copy=1, 6 frames in flight, 1088x1920 max, batch 1. */
+ * threads, zero_copy=1, 6 tasks in flight, 1088x1920 max, batch 1, graphs on. */
 void codec_default_config(codec_config* cfg);
 
 /* Creates a codec from a "LICW" weight blob (see DESIGN notes: per-layer
@@ -119,6 +122,46 @@ void codec_destroy(codec_t* c);
 /* Message describing the last error on this handle (valid until the next
  * call on it).  With c == NULL: the last error of a failed codec_create. */
 const char* codec_last_error(const codec_t* c);
+
+/* ------------------------------------------------------------------------ */
+/* Serving: many concurrent streams of mixed frame sizes (Section VI's       */
+/* streaming use, many cameras to one server).  Requests queue per          */
+/* (direction, frame size) bucket; whenever a pool slot frees up, up to     */
+/* max_batch queued requests of the bucket that has waited longest are      */
+/* admitted as one task and share every GPU launch, while earlier tasks are */
+/* still on the GPU or the entropy workers (continuous batching).  With     */
+/* use_graphs each GPU stage of a (frame size, batch, slot) runs as a       */
+/* captured HIP graph.  A request's result is bit-identical alone and in a  */
+/* batch.  Results come back through codec_poll in completion order.        */
+/* ------------------------------------------------------------------------ */
+typedef struct {
+    uint64_t ticket;
+    int32_t  status;      /* lic_status of the request                          */
+    int32_t  stream_id;
+    int32_t  direction;   /* 0 encode, 1 decode                                 */
+    int32_t  H, W;
+    uint64_t bytes;       /* encode: bitstream length                           */
+    double   latency_ms;  /* submit to result ready                             */
+} lic_result;
+
+/* Admits a stream of H x W frames: reserves its device footprint (one frame
+ * in flight: input, reconstruction and the two largest activations) against
+ * hbm_budget_bytes.  LIC_E_BUDGET if it does not fit or exceeds max_h x max_w. */
+int codec_open_stream(codec_t* c, int H, int W, int* stream_id);
+/* Releases the reservation; requests already queued still complete. */
+int codec_close_stream(codec_t* c, int stream_id);
+/* Queues one frame (3 x H x W float32 at the stream's size) for encoding;
+ * the bitstream goes to out[0..cap) (status LIC_E_SMALLBUF if it does not
+ * fit).  x and out must stay valid until the result is polled. */
+int codec_submit_encode(codec_t* c, int stream_id, const float* x, int is_device,
+                        uint8_t* out, size_t cap, uint64_t* ticket);
+/* Queues one bitstream (validated now) for decoding into x_hat
+ * (3 x H x W float32).  bits and x_hat must stay valid until polled. */
+int codec_submit_decode(codec_t* c, int stream_id, const uint8_t* bits, size_t len,
+                        float* x_hat, size_t cap_elems, int is_device, uint64_t* ticket);
+/* Waits up to timeout_us for completed requests; returns the number written
+ * to done (0 on time-out). */
+int codec_poll(codec_t* c, lic_result* done, int max, int timeout_us);
 
 /* ------------------------------------------------------------------------ */
 /* Stage-level entry points: one layer of the transforms on device buffers,  */

@@ -37,6 +37,20 @@ class CodecConfig(ctypes.Structure):
         ("max_batch", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("hip_device", ctypes.c_int32),
+        ("use_graphs", ctypes.c_int32),
+    ]
+
+
+class LicResult(ctypes.Structure):
+    _fields_ = [
+        ("ticket", ctypes.c_uint64),
+        ("status", ctypes.c_int32),
+        ("stream_id", ctypes.c_int32),
+        ("direction", ctypes.c_int32),
+        ("H", ctypes.c_int32),
+        ("W", ctypes.c_int32),
+        ("bytes", ctypes.c_uint64),
+        ("latency_ms", ctypes.c_double),
     ]
 
 
@@ -60,6 +74,11 @@ SIGNATURES = {
     "lic_rans_decode": (c_int, [P, c_size_t, P, c_long, P, c_int, P]),
     "lic_fnv1a": (c_uint32, [P, c_size_t]),
     "lic_blob_tables": (c_long, [P, c_size_t, c_int, P, c_size_t, P, c_size_t]),
+    "codec_open_stream": (c_int, [P, c_int, c_int, P]),
+    "codec_close_stream": (c_int, [P, c_int]),
+    "codec_submit_encode": (c_int, [P, c_int, P, c_int, P, c_size_t, P]),
+    "codec_submit_decode": (c_int, [P, c_int, P, c_size_t, P, c_size_t, c_int, P]),
+    "codec_poll": (c_int, [P, P, c_int, c_int]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
     _f = getattr(lib, _name)

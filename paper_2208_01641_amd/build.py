@@ -17,7 +17,7 @@ LIB = os.path.join(HERE, "liblic.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HIP_SOURCES = ["conv_kernels.hip"]
-CPP_SOURCES = ["entropy.cpp", "model.cpp", "pipeline.cpp", "api.cpp"]
+CPP_SOURCES = ["entropy.cpp", "model.cpp", "pipeline.cpp", "server.cpp", "api.cpp"]
 
 HIPCC = [os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -39,13 +39,13 @@ class Codec:
     def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1, precision: int = 0,
                  y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 1, max_in_flight: int = 6,
                  max_h: int = 1088, max_w: int = 1920, max_batch: int = 1, hbm_budget_bytes: int = 0,
-                 device: int = 0):
+                 device: int = 0, use_graphs: int = 1):
         cfg = _lib.CodecConfig()
         lib.codec_default_config(ctypes.byref(cfg))
         cfg.kind, cfg.N, cfg.M, cfg.hs_out, cfg.precision = kind, N, M, hs_out, precision
         cfg.y_slices, cfg.entropy_threads, cfg.zero_copy = y_slices, entropy_threads, zero_copy
         cfg.max_in_flight, cfg.max_h, cfg.max_w, cfg.max_batch = max_in_flight, max_h, max_w, max_batch
-        cfg.hbm_budget_bytes, cfg.hip_device = hbm_budget_bytes, device
+        cfg.hbm_budget_bytes, cfg.hip_device, cfg.use_graphs = hbm_budget_bytes, device, use_graphs
         self.cfg = cfg
         self.kind, self.N, self.M, self.S, self.precision = kind, N, M, y_slices, precision
         self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
@@ -139,6 +139,38 @@ class Codec:
         buf = ctypes.create_string_buffer(4096)
         self._check(lib.codec_get_stats(self._h, buf, 4096))
         return json.loads(buf.value.decode())
+
+    # ------------------------------------------------------------ serving
+    def open_stream(self, H: int, W: int) -> int:
+        sid = ctypes.c_int()
+        self._check(lib.codec_open_stream(self._h, H, W, ctypes.byref(sid)))
+        return sid.value
+
+    def close_stream(self, sid: int):
+        self._check(lib.codec_close_stream(self._h, sid))
+
+    def submit_encode(self, sid: int, x, out) -> int:
+        """Queues one frame (3 x H x W float32); the bitstream goes to the
+        uint8 buffer `out`.  Both must stay alive until the result is polled."""
+        t = ctypes.c_uint64()
+        self._check(lib.codec_submit_encode(self._h, sid, _ptr(x), _is_device(x), _ptr(out),
+                                            out.nbytes if hasattr(out, "nbytes") else out.numel(), ctypes.byref(t)))
+        return t.value
+
+    def submit_decode(self, sid: int, bits, x_hat) -> int:
+        """Queues one bitstream (a uint8 numpy array kept alive by the
+        caller) for decoding into x_hat (3 x H x W float32)."""
+        t = ctypes.c_uint64()
+        self._check(lib.codec_submit_decode(self._h, sid, _ptr(bits), bits.size, _ptr(x_hat),
+                                            x_hat.numel() if hasattr(x_hat, "numel") else x_hat.size,
+                                            _is_device(x_hat), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, max_results: int = 256, timeout_us: int = 0) -> list:
+        buf = (_lib.LicResult * max_results)()
+        n = self._check(lib.codec_poll(self._h, buf, max_results, timeout_us))
+        return [{"ticket": r.ticket, "status": r.status, "stream_id": r.stream_id, "direction": r.direction,
+                 "H": r.H, "W": r.W, "bytes": r.bytes, "latency_ms": r.latency_ms} for r in buf[:n]]
 
     def time_layers(self, layers):
         """Bracket every pipeline launch of these layers with HIP events."""

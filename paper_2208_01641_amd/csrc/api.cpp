@@ -43,8 +43,10 @@ void make_tasks(Codec* c, lic::CallState& cs, const float* x, float* x_hat, size
         lic::Task* t = new lic::Task();
         t->first = f;
         t->nb = std::min(B, cs.n - f);
-        t->x = x ? x + (size_t)f * fsz : nullptr;
-        t->xhat = x_hat ? x_hat + (size_t)f * fsz : nullptr;
+        for (int b = 0; b < t->nb; ++b) {
+            t->xs[b] = x ? x + (size_t)(f + b) * fsz : nullptr;
+            t->xhats[b] = x_hat ? x_hat + (size_t)(f + b) * fsz : nullptr;
+        }
         cs.tasks.emplace_back(t);
     }
 }
@@ -73,6 +75,7 @@ void codec_default_config(codec_config* cfg)
     cfg->max_batch = 1;
     cfg->hbm_budget_bytes = 0;
     cfg->hip_device = 0;
+    cfg->use_graphs = 1;
 }
 
 int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, codec_t** out)
@@ -116,10 +119,10 @@ int codec_encode(codec_t* c, const float* x, int n, int H, int W, int is_device,
     if (n > 0 && (!x || !lens)) return fail(c, LIC_E_ARG, "null buffer");
     lic::CallState cs;
     cs.n = n;
-    cs.S = c->S;
-    cs.dims = lic::FrameDims(H, W);
-    cs.is_device = is_device;
-    cs.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC};
+    cs.route.S = c->S;
+    cs.route.dims = lic::FrameDims(H, W);
+    cs.route.is_device = is_device;
+    cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC};
     cs.out = out;
     cs.cap = out ? cap : 0;
     cs.lens = lens;
@@ -154,7 +157,7 @@ int parse_all(Codec* c, const uint8_t* bits, const size_t* lens, int n, lic::Cal
             return fail(c, LIC_E_ARG, "frames of one call must share size and slices");
         off += lens[i];
     }
-    cs.S = (*hdrs)[0].S;
+    cs.route.S = (*hdrs)[0].S;
     return LIC_OK;
 }
 
@@ -182,19 +185,19 @@ int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n, flo
     const size_t fsz = (size_t)3 * h * w;
     if (cap_elems < fsz * n) return fail(c, LIC_E_SMALLBUF, "x_hat capacity too small");
     cs.n = n;
-    cs.dims = lic::FrameDims(h, w);
-    cs.is_device = is_device;
+    cs.route.dims = lic::FrameDims(h, w);
+    cs.route.is_device = is_device;
     if (c->kind == LIC_KIND_HYPERPRIOR)
-        cs.stages = {lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
+        cs.route.stages = {lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     else
-        cs.stages = {lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
+        cs.route.stages = {lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     make_tasks(c, cs, nullptr, x_hat, fsz);
     for (auto& t : cs.tasks)
         for (int b = 0; b < t->nb; ++b) {
             const int f = t->first + b;
             t->zp[b] = zp[f];
             t->zlen[b] = zl[f];
-            for (int s = 0; s < cs.S; ++s) {
+            for (int s = 0; s < cs.route.S; ++s) {
                 t->yp[b][s] = yp[f][s];
                 t->ylen[b][s] = yl[f][s];
             }
@@ -211,13 +214,13 @@ int codec_encode_decode(codec_t* c, const float* x, int n, int H, int W, int is_
     if (n > 0 && (!x || !lens || !x_hat)) return fail(c, LIC_E_ARG, "null buffer");
     lic::CallState cs;
     cs.n = n;
-    cs.S = c->S;
-    cs.dims = lic::FrameDims(H, W);
-    cs.is_device = is_device;
+    cs.route.S = c->S;
+    cs.route.dims = lic::FrameDims(H, W);
+    cs.route.is_device = is_device;
     if (c->kind == LIC_KIND_HYPERPRIOR)
-        cs.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
+        cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     else
-        cs.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
+        cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     cs.out = bits;
     cs.cap = bits ? cap : 0;
     cs.lens = lens;
@@ -348,6 +351,76 @@ int lic_rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n, c
 }
 
 uint32_t lic_fnv1a(const void* data, size_t len) { return lic::fnv1a(data, len); }
+
+int codec_open_stream(codec_t* c, int H, int W, int* stream_id)
+{
+    if (!c || !stream_id) return LIC_E_ARG;
+    return c->open_stream(H, W, stream_id);
+}
+
+int codec_close_stream(codec_t* c, int stream_id)
+{
+    if (!c) return LIC_E_ARG;
+    return c->close_stream(stream_id);
+}
+
+int codec_submit_encode(codec_t* c, int stream_id, const float* x, int is_device, uint8_t* out, size_t cap,
+                        uint64_t* ticket)
+{
+    if (!c || !x || !out || !ticket) return LIC_E_ARG;
+    lic::Request* r = new (std::nothrow) lic::Request();
+    if (!r) return fail(c, LIC_E_NOMEM, "out of memory");
+    r->dir = 0;
+    r->stream_id = stream_id;
+    r->is_device = is_device ? 1 : 0;
+    r->x = x;
+    r->out = out;
+    r->cap = cap;
+    return c->server_submit(r, ticket);   // r is owned by the server from here on
+}
+
+int codec_submit_decode(codec_t* c, int stream_id, const uint8_t* bits, size_t len, float* x_hat, size_t cap_elems,
+                        int is_device, uint64_t* ticket)
+{
+    if (!c || !bits || !x_hat || !ticket) return LIC_E_ARG;
+    lic::Request* r = new (std::nothrow) lic::Request();
+    if (!r) return fail(c, LIC_E_NOMEM, "out of memory");
+    std::vector<const uint8_t*> yp;
+    std::vector<size_t> yl;
+    std::string e;
+    if (!lic::parse_stream(bits, len, &r->hdr, &r->zp, &r->zlen, &yp, &yl, &e)) {
+        delete r;
+        return fail(c, LIC_E_CORRUPT, e);
+    }
+    const lic::StreamHeader& h = r->hdr;
+    if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id) {
+        delete r;
+        return fail(c, LIC_E_MODEL, "bitstream was produced by another model");
+    }
+    if (h.S > lic::kMaxSlices) {
+        delete r;
+        return fail(c, LIC_E_CORRUPT, "too many slices");
+    }
+    if (cap_elems < (size_t)3 * h.H * h.W) {
+        delete r;
+        return fail(c, LIC_E_SMALLBUF, "x_hat capacity too small");
+    }
+    for (int s = 0; s < h.S; ++s) {
+        r->yp[s] = yp[s];
+        r->ylen[s] = yl[s];
+    }
+    r->dir = 1;
+    r->stream_id = stream_id;
+    r->is_device = is_device ? 1 : 0;
+    r->xhat = x_hat;
+    return c->server_submit(r, ticket);
+}
+
+int codec_poll(codec_t* c, lic_result* done, int max, int timeout_us)
+{
+    if (!c || !done || max < 0) return LIC_E_ARG;
+    return c->server_poll(done, max, timeout_us);
+}
 
 long lic_blob_tables(const void* blob, size_t len, int which, uint32_t* freq, size_t cap, float* mu, size_t mu_cap)
 {

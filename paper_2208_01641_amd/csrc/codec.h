@@ -58,18 +58,26 @@ struct Codec;
 constexpr int kMaxSlices = 64;
 constexpr int kMaxBatch = 8;
 
+struct Route;
+struct CallState;
+struct Request;
+
 // A task: up to max_batch consecutive frames of one call that travel
 // together through the stage queues (the state machine of the pipeline).
 // GPU stages launch every layer once for the whole batch; CPU stages split
 // it into per-frame, per-stream jobs.
 struct Task {
+    const Route* route = nullptr;      // frame size, slices, stage list
+    CallState* call = nullptr;         // synchronous call (in-order sink), or
+    Request* req[kMaxBatch] = {};      // serving requests (completion queue)
     int index = 0;                     // position of the task in the call
     int first = 0;                     // index of the first frame in the call
     int nb = 1;                        // frames in this task
     int slot = -1;
-    int stage = -1;                    // index into the call's stage list
-    const float* x = nullptr;          // first input frame (frames are contiguous)
-    float* xhat = nullptr;             // first output frame
+    int stage = -1;                    // index into the route's stage list
+    const float* xs[kMaxBatch] = {};   // input frame of each batch entry
+    float* xhats[kMaxBatch] = {};      // output frame of each batch entry
+    bool staged = false;               // request buffers copied in / out by the caller
     std::atomic<int> jobs_left{0};
     std::atomic<int> status{0};
     std::mutex err_m;
@@ -118,6 +126,14 @@ struct StageScratch {
 };
 
 enum StageKind { ST_GPU_ENC, ST_CPU_ENC, ST_CPU_DEC_Z, ST_GPU_HS, ST_CPU_DEC_Y, ST_GPU_GS };
+
+// What every task of a call (or of a serving bucket) shares.
+struct Route {
+    FrameDims dims;
+    int S = 1;                     // y slices of every frame
+    int is_device = 0;             // caller buffers are device memory
+    std::vector<StageKind> stages;
+};
 
 struct Job {
     Task* task;
@@ -176,10 +192,7 @@ private:
 
 struct CallState {
     int n = 0;                     // frames
-    int S = 1;                     // y slices of every frame in the call
-    FrameDims dims;
-    int is_device = 0;
-    std::vector<StageKind> stages;
+    Route route;
     std::vector<std::unique_ptr<Task>> tasks;
     // in-order sink
     std::mutex m;
@@ -203,11 +216,40 @@ struct GpuStage {
     BlockingQueue<Task*> queue;
     std::thread thread;
     double busy_s = 0.0;
+    bool capturing = false;            // recording a HIP graph (no timing events)
     // events bracketing timed layers: [in-flight task][layer][start/end]
     int cur = 0;
     hipEvent_t lev[2][LIC_NUM_LAYERS][2] = {};
     bool lrec[2][LIC_NUM_LAYERS] = {};
 };
+
+// ---------------------------------------------------------------- serving
+// One asynchronous request (a frame to encode or a bitstream to decode).
+struct Request {
+    uint64_t ticket = 0;
+    int stream_id = 0;
+    int dir = 0;                       // 0 encode, 1 decode
+    int is_device = 0;
+    const float* x = nullptr;          // encode input
+    uint8_t* out = nullptr;            // encode output buffer
+    size_t cap = 0;
+    float* xhat = nullptr;             // decode output
+    // parsed decode input
+    StreamHeader hdr;
+    const uint8_t* zp = nullptr;
+    size_t zlen = 0;
+    const uint8_t* yp[kMaxSlices] = {};
+    size_t ylen[kMaxSlices] = {};
+    double t_submit = 0.0;
+};
+
+struct ServeStream {
+    int H = 0, W = 0;
+    size_t cost = 0;                   // device bytes reserved against the budget
+    bool open = false;
+};
+
+struct Server;
 
 struct Codec {
     codec_config cfg{};
@@ -233,7 +275,6 @@ struct Codec {
     BlockingQueue<int> free_slots;
     BlockingQueue<Job> jobs;
     std::vector<std::thread> workers;
-    CallState* call = nullptr;
     std::vector<double> last_lat_ms;
     double last_wall_s = 0.0;
     int last_frames = 0;
@@ -245,6 +286,18 @@ struct Codec {
     double layer_ms[LIC_NUM_LAYERS] = {};
     long layer_launches[LIC_NUM_LAYERS] = {};
 
+    // serving (continuous batching over per-shape buckets)
+    std::unique_ptr<Server> server;
+    int server_submit(Request* r, uint64_t* ticket);
+    int server_poll(lic_result* out, int max, int timeout_us);
+    void server_finish(Task* t);
+    void server_stop();
+    void server_loop();
+    int open_stream(int H, int W, int* id);
+    int close_stream(int id);
+    int gpu_stage_graph(Task* t, GpuStage& G, int (Codec::*body)(Task*, GpuStage&));
+
+    Codec();
     ~Codec();
     // model
     int load(const void* blob, size_t len);
@@ -265,7 +318,7 @@ struct Codec {
     int gpu_hs(Task* t, GpuStage& g);
     int gpu_gs(Task* t, GpuStage& g);
     int cpu_job(Task* t, int frame, int part);
-    int cpu_parts(StageKind k) const;          // jobs per frame
+    int cpu_parts(const Task* t, StageKind k) const;   // jobs per frame
     int cpu_finalize(Task* t, StageKind k);
     // allocation helpers (create time only)
     void* dev_alloc(size_t bytes);

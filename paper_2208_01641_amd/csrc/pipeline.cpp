@@ -43,7 +43,7 @@ double now_s()
 
 #define LAUNCH(layer, in, out, aux, stream)                                        \
     do {                                                                           \
-        const bool timed_ = (timed_mask.load() >> (layer)) & 1u;                    \
+        const bool timed_ = !G.capturing && ((timed_mask.load() >> (layer)) & 1u);  \
         if (timed_) (void)hipEventRecord(G.lev[G.cur][layer][0], stream);          \
         std::string e_;                                                            \
         int r_ = launch_layer(layer, t->nb, d, in, out, aux, stream, &e_);         \
@@ -162,36 +162,26 @@ void Codec::stop()
     started = false;
 }
 
-Codec::~Codec()
-{
-    stop();
-    if (hipSetDevice(cfg.hip_device) == hipSuccess) (void)hipDeviceSynchronize();
-    for (int g = 0; g < 3; ++g)
-        if (gpu[g].stream) (void)hipStreamDestroy(gpu[g].stream);
-    if (layer_stream) (void)hipStreamDestroy(layer_stream);
-    for (void* p : dev_allocs) (void)hipFree(p);
-    for (void* p : host_allocs) (void)hipHostFree(p);
-}
 
 // ------------------------------------------------------------- dispatch
 void Codec::advance(Task* t)
 {
-    CallState& cs = *call;
+    const Route& rt = *t->route;
     if (t->status.load() != 0) {
         finish_task(t);
         return;
     }
     t->stage++;
-    if (t->stage >= (int)cs.stages.size()) {
+    if (t->stage >= (int)rt.stages.size()) {
         finish_task(t);
         return;
     }
-    const StageKind k = cs.stages[t->stage];
+    const StageKind k = rt.stages[t->stage];
     const int g = stage_gpu_index(k);
     if (g >= 0) {
         gpu[g].queue.push(t);
     } else {
-        const int parts = cpu_parts(k) * t->nb;
+        const int parts = cpu_parts(t, k) * t->nb;
         t->jobs_left.store(parts);
         for (int p = 0; p < parts; ++p) jobs.push(Job{t, p});
     }
@@ -199,8 +189,12 @@ void Codec::advance(Task* t)
 
 void Codec::finish_task(Task* t)
 {
-    CallState& cs = *call;
     t->t_done = now_s();
+    if (!t->call) {
+        server_finish(t);
+        return;
+    }
+    CallState& cs = *t->call;
     std::lock_guard<std::mutex> g(cs.m);
     cs.finished[t->index] = 1;
     while (cs.next_sink < (int)cs.tasks.size() && cs.finished[cs.next_sink]) {
@@ -272,9 +266,31 @@ void Codec::gpu_loop(int gi)
         }
         (void)hipEventRecord(ev_start[cur_ev], G.stream);
         G.cur = cur_ev;
-        if (G.kind == ST_GPU_ENC) gpu_encode(t, G);
-        else if (G.kind == ST_GPU_HS) gpu_hs(t, G);
-        else gpu_gs(t, G);
+        int (Codec::*body)(Task*, GpuStage&) =
+            G.kind == ST_GPU_ENC ? &Codec::gpu_encode : G.kind == ST_GPU_HS ? &Codec::gpu_hs : &Codec::gpu_gs;
+        if (!t->call && cfg.use_graphs) {
+            // serving: request buffers in and out around a per-(stage, size,
+            // batch, slot) graph that only touches pool buffers
+            const FrameDims& d = t->route->dims;
+            const size_t fsz = (size_t)3 * d.H * d.W;
+            const hipMemcpyKind kin = t->route->is_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+            const hipMemcpyKind kout = t->route->is_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+            bool ok = true;
+            if (G.kind == ST_GPU_ENC)
+                for (int b = 0; b < t->nb && ok; ++b)
+                    ok = hipMemcpyAsync(slots[t->slot].d_x + b * fsz, t->xs[b], fsz * sizeof(float), kin, G.stream) ==
+                         hipSuccess;
+            t->staged = true;
+            if (!ok) t->fail(LIC_E_HIP, "input copy failed");
+            else if (gpu_stage_graph(t, G, body) == LIC_OK && G.kind == ST_GPU_GS)
+                for (int b = 0; b < t->nb && ok; ++b)
+                    ok = hipMemcpyAsync(t->xhats[b], slots[t->slot].d_xhat + b * fsz, fsz * sizeof(float), kout,
+                                        G.stream) == hipSuccess;
+            if (!ok) t->fail(LIC_E_HIP, "output copy failed");
+        } else {
+            t->staged = false;
+            (this->*body)(t, G);
+        }
         (void)hipEventRecord(ev_end[cur_ev], G.stream);
         if (pending) complete(pending, pend_ev);
         pending = t;
@@ -292,16 +308,31 @@ void Codec::gpu_loop(int gi)
     }
 }
 
+// Frames of a task read in place when they are contiguous device memory,
+// else gathered into the slot's staging buffer.
+static bool frames_contiguous(const Task* t, size_t fsz, bool out)
+{
+    for (int b = 1; b < t->nb; ++b)
+        if (out ? t->xhats[b] != t->xhats[0] + b * fsz : t->xs[b] != t->xs[0] + b * fsz) return false;
+    return true;
+}
+
 int Codec::gpu_encode(Task* t, GpuStage& G)
 {
-    const FrameDims& d = call->dims;
+    const FrameDims& d = t->route->dims;
     Slot& s = slots[t->slot];
     StageScratch& sc = G.scratch;
     hipStream_t st = G.stream;
     const size_t ny = (size_t)t->nb * d.Hy * d.Wy * M, nz = (size_t)t->nb * d.Hz * d.Wz * N;
-    const float* x = t->x;
-    if (!call->is_device) {
-        HIP_OK(hipMemcpyAsync(s.d_x, t->x, (size_t)t->nb * 3 * d.H * d.W * sizeof(float), hipMemcpyHostToDevice, st));
+    const size_t fsz = (size_t)3 * d.H * d.W;
+    const bool dev = t->route->is_device != 0;
+    const float* x = t->xs[0];
+    if (t->staged) {
+        x = s.d_x;
+    } else if (!dev || !t->call || !frames_contiguous(t, fsz, false)) {
+        for (int b = 0; b < t->nb; ++b)
+            HIP_OK(hipMemcpyAsync(s.d_x + b * fsz, t->xs[b], fsz * sizeof(float),
+                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice, st));
         x = s.d_x;
     }
     const bool zc = cfg.zero_copy != 0;
@@ -326,7 +357,7 @@ int Codec::gpu_encode(Task* t, GpuStage& G)
 
 int Codec::gpu_hs(Task* t, GpuStage& G)
 {
-    const FrameDims& d = call->dims;
+    const FrameDims& d = t->route->dims;
     Slot& s = slots[t->slot];
     StageScratch& sc = G.scratch;
     hipStream_t st = G.stream;
@@ -342,30 +373,34 @@ int Codec::gpu_hs(Task* t, GpuStage& G)
 
 int Codec::gpu_gs(Task* t, GpuStage& G)
 {
-    const FrameDims& d = call->dims;
+    const FrameDims& d = t->route->dims;
     Slot& s = slots[t->slot];
     StageScratch& sc = G.scratch;
     hipStream_t st = G.stream;
     const size_t ny = (size_t)t->nb * d.Hy * d.Wy * M;
+    const size_t fsz = (size_t)3 * d.H * d.W;
+    const bool dev = t->route->is_device != 0;
+    const bool direct = !t->staged && dev && t->call && frames_contiguous(t, fsz, true);
     HIP_OK(hipMemcpyAsync(s.d_sym_y, s.h_sym_y, ny, hipMemcpyHostToDevice, st));
-    float* xo = call->is_device ? t->xhat : s.d_xhat;
+    float* xo = direct ? t->xhats[0] : s.d_xhat;
     LAUNCH(LIC_GS0, s.d_sym_y, sc.a, nullptr, st);
     LAUNCH(LIC_GS1, sc.a, sc.b, nullptr, st);
     LAUNCH(LIC_GS2, sc.b, sc.a, nullptr, st);
     LAUNCH(LIC_GS3, sc.a, xo, nullptr, st);
-    if (!call->is_device)
-        HIP_OK(hipMemcpyAsync(t->xhat, s.d_xhat, (size_t)t->nb * 3 * d.H * d.W * sizeof(float),
-                              hipMemcpyDeviceToHost, st));
+    if (!direct && !t->staged)
+        for (int b = 0; b < t->nb; ++b)
+            HIP_OK(hipMemcpyAsync(t->xhats[b], s.d_xhat + b * fsz, fsz * sizeof(float),
+                                  dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
     return LIC_OK;
 }
 
 // ------------------------------------------------------------- CPU side
-int Codec::cpu_parts(StageKind k) const
+int Codec::cpu_parts(const Task* t, StageKind k) const
 {
     switch (k) {
-    case ST_CPU_ENC: return call->S + (kind == 1 ? 1 : 0);
+    case ST_CPU_ENC: return t->route->S + (kind == 1 ? 1 : 0);
     case ST_CPU_DEC_Z: return 1;
-    case ST_CPU_DEC_Y: return call->S;
+    case ST_CPU_DEC_Y: return t->route->S;
     default: return 0;
     }
 }
@@ -375,8 +410,8 @@ void Codec::worker_loop()
     Job j;
     while (jobs.pop(&j)) {
         Task* t = j.task;
-        const StageKind k = call->stages[t->stage];
-        const int ppf = cpu_parts(k);
+        const StageKind k = t->route->stages[t->stage];
+        const int ppf = cpu_parts(t, k);
         const double t0 = now_s();
         if (t->status.load() == 0) cpu_job(t, j.part / ppf, j.part % ppf);
         cpu_busy_us += (long)((now_s() - t0) * 1e6);
@@ -396,10 +431,10 @@ static inline void slice_rows(int Hy, int S, int s, int* r0, int* r1)
 
 int Codec::cpu_job(Task* t, int b, int part)
 {
-    const FrameDims& d = call->dims;
+    const FrameDims& d = t->route->dims;
     Slot& s = slots[t->slot];
-    const StageKind k = call->stages[t->stage];
-    const int S = call->S;
+    const StageKind k = t->route->stages[t->stage];
+    const int S = t->route->S;
     const size_t row = (size_t)d.Wy * M;
     const size_t ny = (size_t)d.Hy * row, nz = kind == 1 ? (size_t)d.Hz * d.Wz * N : 0;
     int8_t* sym_y = s.h_sym_y + (size_t)b * ny;        // frame b of the task (current size)
@@ -452,8 +487,8 @@ int Codec::cpu_job(Task* t, int b, int part)
 int Codec::cpu_finalize(Task* t, StageKind k)
 {
     if (k != ST_CPU_ENC) return LIC_OK;
-    const FrameDims& d = call->dims;
-    const int S = call->S;
+    const FrameDims& d = t->route->dims;
+    const int S = t->route->S;
     Slot& s = slots[t->slot];
     const size_t row = (size_t)d.Wy * M;
     const size_t nz = kind == 1 ? (size_t)d.Hz * d.Wz * N : 0;
@@ -507,13 +542,20 @@ int Codec::cpu_finalize(Task* t, StageKind k)
 // them one slot at a time and waits for the in-order sink to drain.
 int Codec::run_call(CallState& cs)
 {
-    call = &cs;
     cs.finished.assign(cs.tasks.size(), 0);
     const double t0 = now_s();
     for (size_t i = 0; i < cs.tasks.size(); ++i) {
         int slot;
-        if (!free_slots.pop(&slot)) { call = nullptr; err = "codec stopped"; return LIC_E_STATE; }
+        if (!free_slots.pop(&slot)) {
+            // should not happen: the pool is only closed at destroy; drain what was admitted
+            std::unique_lock<std::mutex> g(cs.m);
+            cs.cv.wait(g, [&] { return cs.done == (int)i; });
+            err = "codec stopped";
+            return LIC_E_STATE;
+        }
         Task* t = cs.tasks[i].get();
+        t->route = &cs.route;
+        t->call = &cs;
         t->index = (int)i;
         t->slot = slot;
         t->stage = -1;
@@ -529,7 +571,6 @@ int Codec::run_call(CallState& cs)
     last_lat_ms.assign(cs.n, 0.0);
     for (auto& up : cs.tasks)
         for (int b = 0; b < up->nb; ++b) last_lat_ms[up->first + b] = (up->t_done - up->t_admit) * 1e3;
-    call = nullptr;
     if (cs.status != 0) {
         err = cs.err;
         return cs.status;

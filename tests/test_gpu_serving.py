@@ -1,0 +1,111 @@
+"""Serving: continuous batching of mixed-size streams (C ABI submit / poll).
+
+Each request's bitstream and reconstruction must be bit-identical to the
+same frame coded alone through the synchronous path (eager launches, batch
+1), whatever it was batched with and however many times the captured graphs
+were replayed.  Admission by the device-memory budget refuses a stream that
+does not fit, and serving allocates no device memory after warm-up.
+"""
+import time
+
+import numpy as np
+import pytest
+
+import synth
+from gpu_util import make_codec
+
+pytestmark = pytest.mark.gpu
+
+SIZES = [(128, 192), (192, 256), (128, 192)]     # stream 0 and 2 share a bucket
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available()
+    return torch
+
+
+def _drain(c, n, timeout_s=60.0):
+    res = []
+    t0 = time.time()
+    while len(res) < n:
+        res += c.poll(256, 20000)
+        assert time.time() - t0 < timeout_s, "serving results did not arrive"
+    return res
+
+
+@pytest.mark.parametrize("use_graphs", [1, 0])
+def test_mixed_streams_equal_alone(torch_dev, use_graphs):
+    torch = torch_dev
+    alone, _ = make_codec(1, 128, 192, max_h=192, max_w=256, y_slices=2, entropy_threads=4, max_in_flight=2)
+    srv, _ = make_codec(1, 128, 192, max_h=192, max_w=256, y_slices=2, entropy_threads=6, max_in_flight=3,
+                        max_batch=3, use_graphs=use_graphs)
+    frames = {s: [torch.from_numpy(synth.frame_sinusoid(H, W, t=t, stream=s)).cuda() for t in range(5)]
+              for s, (H, W) in enumerate(SIZES)}
+    # references: each frame alone, synchronous path
+    ref_bits, ref_img = {}, {}
+    for s, (H, W) in enumerate(SIZES):
+        for t, x in enumerate(frames[s]):
+            b = alone.encode(x[None])[0]
+            o = torch.empty((1, 3, H, W), device="cuda")
+            alone.decode([b], o)
+            ref_bits[(s, t)], ref_img[(s, t)] = b, o[0]
+    sids = [srv.open_stream(H, W) for H, W in SIZES]
+    allocs = None
+    for rep in range(3):                       # graphs are replayed on later rounds
+        outs, tick = {}, {}
+        for t in range(5):                     # interleave the streams
+            for s, sid in enumerate(sids):
+                buf = np.zeros(srv.max_stream_bytes(*SIZES[s]), np.uint8)
+                outs[(s, t)] = buf
+                tick[srv.submit_encode(sid, frames[s][t], buf)] = (s, t)
+        res = _drain(srv, len(tick))
+        bits = {}
+        for r in res:
+            assert r["status"] == 0 and r["direction"] == 0
+            key = tick[r["ticket"]]
+            bits[key] = outs[key][:r["bytes"]].tobytes()
+            assert bits[key] == ref_bits[key], f"encode {key} differs from the frame coded alone"
+        # decode them back, mixed
+        imgs, dtick, keep = {}, {}, []
+        for key, b in bits.items():
+            s, t = key
+            H, W = SIZES[s]
+            arr = np.frombuffer(b, np.uint8).copy()
+            keep.append(arr)
+            imgs[key] = torch.empty((3, H, W), device="cuda")
+            dtick[srv.submit_decode(sids[s], arr, imgs[key])] = key
+        for r in _drain(srv, len(dtick)):
+            assert r["status"] == 0 and r["direction"] == 1
+            key = dtick[r["ticket"]]
+            assert torch.equal(imgs[key], ref_img[key]), f"decode {key} differs from the frame decoded alone"
+        torch.cuda.synchronize()
+        st = srv.stats()
+        if allocs is None:
+            allocs = st["alloc_events"]
+        assert st["alloc_events"] == allocs, "device memory allocated on the serving path"
+    for sid in sids:
+        srv.close_stream(sid)
+    srv.close()
+    alone.close()
+
+
+def test_admission_by_budget(torch_dev):
+    from paper_2208_01641_amd import LicError
+    c, _ = make_codec(1, 128, 192, max_h=256, max_w=256, y_slices=1, entropy_threads=2, max_in_flight=1)
+    base = c.stats()["device_bytes"]
+    c.close()
+    one = 4 * (6 * 256 * 256 + 128 * 128 * 128 + 128 * 64 * 64)     # one 256x256 stream's reservation
+    c, _ = make_codec(1, 128, 192, max_h=256, max_w=256, y_slices=1, entropy_threads=2, max_in_flight=1,
+                      hbm_budget_bytes=base + 2 * one + one // 2)
+    a = c.open_stream(256, 256)
+    b = c.open_stream(256, 256)
+    with pytest.raises(LicError) as e:
+        c.open_stream(256, 256)
+    assert e.value.code == -6                     # LIC_E_BUDGET
+    c.close_stream(a)
+    c.open_stream(256, 256)                       # fits again once a stream closed
+    with pytest.raises(LicError):
+        c.open_stream(512, 256)                   # larger than max_h x max_w
+    c.close()
