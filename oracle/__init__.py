@@ -74,6 +74,10 @@ def lib():
         L.or_conv2d_points.argtypes = [P, i, i, i, P, P, i, i, i, i, i, P, P]
         L.or_deconv2d_points.restype = None
         L.or_deconv2d_points.argtypes = [P, i, i, i, P, P, i, i, i, i, i, P, P]
+        L.or_deconv2d_wgrad.restype = None
+        L.or_deconv2d_wgrad.argtypes = [P, i, i, i, P, i, i, i, i, i, i, P, P]
+        L.or_adamw.restype = None
+        L.or_adamw.argtypes = [P, P, P, P, l, l, d, d, d, d, d]
         L.or_gdn.restype = None
         L.or_gdn.argtypes = [P, i, l, P, P, i, P]
         L.or_density_logit.restype = d
@@ -526,6 +530,80 @@ def parse_container(bits: bytes) -> dict:
         pos += ln
     hdr["y"] = ys
     return hdr
+
+
+# ----------------------------------------------------------------------------
+# distilled synthesis network (a learned stand-in for g_s)
+#   T1: transposed conv 5x5 s2 p2 op1, M -> F, ReLU
+#   T2: transposed conv 5x5 s2 p2 op1, F -> F, ReLU
+#   T3: transposed conv 8x8 s4 p2,     F -> 3
+# so a latent of Hy x Wy maps to 16 Hy x 16 Wy pixels, like g_s.
+# ----------------------------------------------------------------------------
+DISTILL_LAYERS = (("t1", 5, 2, 2, 1), ("t2", 5, 2, 2, 1), ("t3", 8, 4, 2, 0))   # name, k, s, p, output padding
+
+
+def deconv2d_wgrad(x, dy, k: int, s: int, p: int):
+    """Gradients of a transposed convolution's weights [C_in, C_out, k, k]
+    and bias for one image x [C_in, H, W] and output gradient dy."""
+    x, dy = _f64(x), _f64(dy)
+    C, H, W = x.shape
+    Co, Ho, Wo = dy.shape
+    dw = np.zeros((C, Co, k, k))
+    db = np.zeros(Co)
+    lib().or_deconv2d_wgrad(_p(x), C, H, W, _p(dy), Co, Ho, Wo, k, s, p, _p(dw), _p(db))
+    return dw, db
+
+
+def deconv2d_dgrad(dy, w, s: int, p: int, H: int, W: int):
+    """Gradient of a transposed convolution's input: the strided convolution
+    of dy with the same weights read as [C_out = C_in, C_in = C_out, k, k],
+    cropped to the input size."""
+    g = conv2d(dy, w, None, s, p)
+    return g[:, :H, :W]
+
+
+def distill_forward(P, yhat):
+    """yhat [B, M, Hy, Wy] -> (out [B, 3, 16Hy, 16Wy], activations)."""
+    outs, acts = [], []
+    for n in range(yhat.shape[0]):
+        h = _f64(yhat[n])
+        a = [h]
+        for name, k, s, p, op in DISTILL_LAYERS:
+            h = deconv2d(h, P[name + ".w"], P[name + ".b"], s, p, op)
+            if name != "t3":
+                h = relu(h)
+            a.append(h)
+        outs.append(h)
+        acts.append(a)
+    return np.stack(outs), acts
+
+
+def distill_loss_and_grads(P, yhat, target):
+    """MSE over every output element and its gradients (FP64)."""
+    out, acts = distill_forward(P, yhat)
+    n = out.size
+    loss = float(np.mean((out - target) ** 2))
+    grads = {k: np.zeros_like(np.asarray(v, np.float64)) for k, v in P.items()}
+    for b in range(out.shape[0]):
+        g = 2.0 * (out[b] - target[b]) / n
+        for li in (2, 1, 0):
+            name, k, s, p, op = DISTILL_LAYERS[li]
+            x_in = acts[b][li]
+            dw, db = deconv2d_wgrad(x_in, g, k, s, p)
+            grads[name + ".w"] += dw
+            grads[name + ".b"] += db
+            if li > 0:
+                g = deconv2d_dgrad(g, P[name + ".w"], s, p, x_in.shape[1], x_in.shape[2])
+                g = g * (x_in > 0)              # ReLU of the previous layer
+    return loss, grads
+
+
+def adamw_step(w, m, v, g, t: int, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8, wd=0.01):
+    """In place, on float64 arrays; t counts from 1."""
+    for a in (w, m, v):
+        assert a.dtype == np.float64 and a.flags.c_contiguous
+    g = _f64(g)
+    lib().or_adamw(_p(w), _p(m), _p(v), _p(g), w.size, t, lr, b1, b2, eps, wd)
 
 
 def psnr(x, xr) -> float:

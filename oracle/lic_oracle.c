@@ -124,6 +124,51 @@ void or_deconv2d_points(const double* in, int C, int H, int W,
             out[(long)q * Co + o] = or_deconv2d_at(in, C, H, W, w, b, Co, k, s, p, o, ij[2 * q], ij[2 * q + 1]);
 }
 
+/* Weight gradient of a transposed convolution (weights [C_in, C_out, k, k]) */
+/* for one image:  dW[c,o,u,v] += sum_{a,b} x[c,a,b] dy[o, s a + u - p, s b + v - p] */
+/* over output positions inside dy; db[o] += sum of dy[o].  Accumulates.    */
+void or_deconv2d_wgrad(const double* x, int C, int H, int W, const double* dy, int Co, int Ho, int Wo,
+                       int k, int s, int p, double* dw, double* db)
+{
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int c = 0; c < C; ++c)
+        for (int o = 0; o < Co; ++o)
+            for (int u = 0; u < k; ++u)
+                for (int v = 0; v < k; ++v) {
+                    double acc = 0.0;
+                    for (int a = 0; a < H; ++a) {
+                        int i = s * a + u - p;
+                        if (i < 0 || i >= Ho) continue;
+                        for (int b = 0; b < W; ++b) {
+                            int j = s * b + v - p;
+                            if (j < 0 || j >= Wo) continue;
+                            acc += x[((long)c * H + a) * W + b] * dy[((long)o * Ho + i) * Wo + j];
+                        }
+                    }
+                    dw[(((long)c * Co + o) * k + u) * k + v] += acc;
+                }
+    if (db)
+        for (int o = 0; o < Co; ++o) {
+            double acc = 0.0;
+            for (long q = 0; q < (long)Ho * Wo; ++q) acc += dy[(long)o * Ho * Wo + q];
+            db[o] += acc;
+        }
+}
+
+/* One AdamW step with decoupled weight decay and bias correction, step t  */
+/* counted from 1:  m <- b1 m + (1-b1) g;  v <- b2 v + (1-b2) g^2;         */
+/* w <- w (1 - lr wd) - lr (m / (1-b1^t)) / (sqrt(v / (1-b2^t)) + eps).    */
+void or_adamw(double* w, double* m, double* v, const double* g, long n, long t,
+              double lr, double b1, double b2, double eps, double wd)
+{
+    const double c1 = 1.0 - pow(b1, (double)t), c2 = 1.0 - pow(b2, (double)t);
+    for (long i = 0; i < n; ++i) {
+        m[i] = b1 * m[i] + (1.0 - b1) * g[i];
+        v[i] = b2 * v[i] + (1.0 - b2) * g[i] * g[i];
+        w[i] = w[i] * (1.0 - lr * wd) - lr * (m[i] / c1) / (sqrt(v[i] / c2) + eps);
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* GDN / IGDN, per pixel over channels.  x and out are [C][HW] planes.      */
 /*   n_i = beta_i + sum_j gamma[i][j] x_j^2                                 */

@@ -201,6 +201,19 @@ def density_params(C: int, rng) -> np.ndarray:
     return out
 
 
+def distill_params(M: int = 192, F: int = 64, seed: int = WEIGHT_SEED + 1) -> "OrderedDict[str, np.ndarray]":
+    """Initial parameters of the distilled synthesis network (three
+    transposed convolutions M -> F -> F -> 3 with kernels 5, 5, 8):
+    He-normal weights [C_in, C_out, k, k] and U(-0.05, 0.05) biases."""
+    rng = np.random.default_rng(seed)
+    P: "OrderedDict[str, np.ndarray]" = OrderedDict()
+    for name, cin, cout, k in (("t1", M, F, 5), ("t2", F, F, 5), ("t3", F, 3, 8)):
+        std = math.sqrt(2.0 / (cin * k * k))
+        P[name + ".w"] = (rng.standard_normal((cin, cout, k, k)) * std).astype(np.float32)
+        P[name + ".b"] = rng.uniform(-0.05, 0.05, cout).astype(np.float32)
+    return P
+
+
 def weight_blob(params: "OrderedDict[str, np.ndarray]", kind: int, N: int, M: int) -> bytes:
     """Serialise parameters as the little-endian "LICW" container.
 
