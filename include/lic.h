@@ -212,6 +212,80 @@ long codec_tables(const codec_t* c, int which, uint32_t* freq, size_t cap);
 long codec_medians(const codec_t* c, float* mu, size_t cap);
 
 /* ------------------------------------------------------------------------ */
+/* Distilled synthesis transform: a smaller learned stand-in for g_s.       */
+/*                                                                          */
+/* The paper points to optimisations of the neural model itself as the     */
+/* complement of its system architecture (Sections I and VI).  This net     */
+/* maps y_hat (M channels) to the image with three transposed convolutions */
+/* of F hidden channels: T(M->F, 5x5, stride 2, pad 2, output pad 1), ReLU, */
+/* T(F->F, same), ReLU, T(F->3, 8x8, stride 4, pad 2): 16x upsampling, the  */
+/* same as g_s.  It is trained on the GPU, by these entry points, to match */
+/* the full g_s (mean squared error, AdamW), and can replace g_s in the     */
+/* codec's decoder (codec_load_distilled).                                  */
+/*                                                                          */
+/* Parameters are one float32 array in this order: t1.w [M][F][5][5],      */
+/* t1.b [F], t2.w [F][F][5][5], t2.b [F], t3.w [F][3][8][8], t3.b [3]       */
+/* (transposed-convolution weights are [C_in][C_out][k][k]).  The handle    */
+/* keeps an FP32 master copy with the AdamW moments; forward passes use     */
+/* FP32 or bf16 GEMM operands (precision), gradients are FP32.  All tensor  */
+/* arguments are device pointers on the handle's device unless stated.      */
+/* ------------------------------------------------------------------------ */
+typedef struct lic_distill lic_distill_t;
+
+typedef struct {
+    uint32_t struct_size;      /* sizeof(lic_distill_config)                         */
+    int32_t  M, F;             /* latent channels (192 or 320), hidden channels (64) */
+    int32_t  precision;        /* forward GEMM operands: LIC_PREC_FP32 / _BF16;      */
+                               /* training (grads / step) requires LIC_PREC_FP32     */
+    int32_t  max_batch;        /* largest n of any call                              */
+    int32_t  max_hy, max_wy;   /* largest latent grid (image = 16 hy x 16 wy)        */
+    int32_t  train;            /* 1: allocate gradient and optimizer state           */
+    float    lr, beta1, beta2, eps, weight_decay;   /* AdamW                         */
+    int32_t  hip_device;
+} lic_distill_config;
+
+/* M 192, F 64, FP32, batch 32, 16 x 16 latents, training on, lr 1e-3,
+ * betas (0.9, 0.999), eps 1e-8, weight decay 0.01, device 0. */
+void   lic_distill_default_config(lic_distill_config* cfg);
+/* Number of float32 parameters for (M, F). */
+size_t lic_distill_param_count(int M, int F);
+/* params: host array of lic_distill_param_count(M, F) floats (copied). */
+int    lic_distill_create(const lic_distill_config* cfg, const float* params, size_t n_params,
+                          lic_distill_t** out);
+void   lic_distill_destroy(lic_distill_t* d);
+const char* lic_distill_last_error(const lic_distill_t* d);
+/* Forward pass of n latents.  sym: int8 symbols NHWC [n][hy][wy][M] with
+ * y_hat = sym + mu[c] (mu: M floats on the device, NULL = 0).  pre: NULL or
+ * the unclamped output NCHW [n][3][16 hy][16 wy]; x_hat: NULL or the image
+ * clamped to [0, 1] and cropped to H x W (NCHW [n][3][H][W]).  Runs on the
+ * handle's stream and waits for it. */
+int lic_distill_forward(lic_distill_t* d, const int8_t* sym, const float* mu, int n, int hy, int wy,
+                        float* pre, float* x_hat, int H, int W);
+/* Loss (mean squared error of the unclamped output against target, NCHW
+ * [n][3][16 hy][16 wy]) and its gradient w.r.t. every parameter, without an
+ * update.  grads: host array of param_count floats, or NULL; loss: host. */
+int lic_distill_grads(lic_distill_t* d, const int8_t* sym, const float* mu, const float* target, int n,
+                      int hy, int wy, float* grads, float* loss);
+/* One training step on a batch drawn from a device-resident data set of
+ * pairs (sym_all [count][hy][wy][M], target_all [count][3][16 hy][16 wy]):
+ * idx (host, n entries < count) selects the samples, which are gathered on
+ * the device; then forward, loss, backward and one AdamW update.  The loss
+ * of the step goes to loss_dev[0] (device float, may be NULL).  Does not
+ * wait for the GPU. */
+int lic_distill_step(lic_distill_t* d, const int8_t* sym_all, const float* mu, const float* target_all,
+                     long count, const int32_t* idx, int n, int hy, int wy, float* loss_dev);
+/* Waits for every step issued so far. */
+int lic_distill_sync(lic_distill_t* d);
+/* Host copies of the state: what 0 = parameters, 1 = first moments,
+ * 2 = second moments, 3 = last gradients; each param_count floats. */
+int lic_distill_get(lic_distill_t* d, int what, float* out, size_t n);
+/* Replaces parameters (what 0) or moments (1, 2) from host memory. */
+int lic_distill_set(lic_distill_t* d, int what, const float* in, size_t n);
+/* AdamW step counter (for resuming from a checkpoint). */
+int lic_distill_get_step(lic_distill_t* d, int64_t* t);
+int lic_distill_set_step(lic_distill_t* d, int64_t t);
+
+/* ------------------------------------------------------------------------ */
 /* Host entropy primitives (no GPU needed).                                 */
 /* ------------------------------------------------------------------------ */
 /* Byte-wise rANS (32-bit state, L = 2^23, 16-bit frequencies).  sym holds

@@ -41,6 +41,25 @@ class CodecConfig(ctypes.Structure):
     ]
 
 
+class DistillConfig(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("M", ctypes.c_int32),
+        ("F", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("max_hy", ctypes.c_int32),
+        ("max_wy", ctypes.c_int32),
+        ("train", ctypes.c_int32),
+        ("lr", ctypes.c_float),
+        ("beta1", ctypes.c_float),
+        ("beta2", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("weight_decay", ctypes.c_float),
+        ("hip_device", ctypes.c_int32),
+    ]
+
+
 class LicResult(ctypes.Structure):
     _fields_ = [
         ("ticket", ctypes.c_uint64),
@@ -79,6 +98,19 @@ SIGNATURES = {
     "codec_submit_encode": (c_int, [P, c_int, P, c_int, P, c_size_t, P]),
     "codec_submit_decode": (c_int, [P, c_int, P, c_size_t, P, c_size_t, c_int, P]),
     "codec_poll": (c_int, [P, P, c_int, c_int]),
+    "lic_distill_default_config": (None, [P]),
+    "lic_distill_param_count": (c_size_t, [c_int, c_int]),
+    "lic_distill_create": (c_int, [P, P, c_size_t, P]),
+    "lic_distill_destroy": (None, [P]),
+    "lic_distill_last_error": (ctypes.c_char_p, [P]),
+    "lic_distill_forward": (c_int, [P, P, P, c_int, c_int, c_int, P, P, c_int, c_int]),
+    "lic_distill_grads": (c_int, [P, P, P, P, c_int, c_int, c_int, P, P]),
+    "lic_distill_step": (c_int, [P, P, P, P, c_long, P, c_int, c_int, c_int, P]),
+    "lic_distill_sync": (c_int, [P]),
+    "lic_distill_get": (c_int, [P, c_int, P, c_size_t]),
+    "lic_distill_set": (c_int, [P, c_int, P, c_size_t]),
+    "lic_distill_get_step": (c_int, [P, P]),
+    "lic_distill_set_step": (c_int, [P, ctypes.c_int64]),
 }
 for _name, (_res, _args) in SIGNATURES.items():
     _f = getattr(lib, _name)

@@ -16,8 +16,8 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblic.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["conv_kernels.hip"]
-CPP_SOURCES = ["entropy.cpp", "model.cpp", "pipeline.cpp", "server.cpp", "api.cpp"]
+HIP_SOURCES = ["conv_kernels.hip", "distill_kernels.hip"]
+CPP_SOURCES = ["entropy.cpp", "packing.cpp", "model.cpp", "pipeline.cpp", "server.cpp", "api.cpp", "distill.cpp"]
 
 HIPCC = [os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

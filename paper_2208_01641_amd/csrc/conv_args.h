@@ -9,7 +9,8 @@ enum Loader : int {
     LD_F32 = 0,      // float NHWC activations
     LD_F32_ABS = 1,  // |float| NHWC (h_a takes |y|)
     LD_I8 = 2,       // int8 NHWC symbols, dequantised as sym + mu[c]
-    LD_RGB = 3,      // float NCHW 3-channel image, unpadded (ingest + zero pad)
+    LD_RGB = 3,      // float NCHW 3-channel tensor, kk x kk taps flattened with the
+                     // channels (image ingest with its zero pad; 3-channel gradients)
 };
 
 // Epilogues fused after the K loop.
@@ -20,8 +21,9 @@ enum Epilogue : int {
     EP_IGDN = 3,     // y = x * sqrt(beta + gamma (x*x))
     EP_QUANT = 4,    // out = v (float), aux = clamp(rne(v - mu[c]), -64, 64) int8
     EP_INDEX = 5,    // out = scale-table index uint8, aux = v (float, optional)
-    EP_RGB = 6,      // transposed conv to 3 channels, 4 phases as 12 GEMM rows:
-                     // out = clamp(v, 0, 1) cropped NCHW, aux = v padded NCHW
+    EP_RGB = 6,      // transposed conv to 3 channels, all S x S phases as 3 S^2
+                     // GEMM rows: out = clamp(v, 0, 1) cropped NCHW, aux = v NCHW
+    EP_MASK = 7,     // out = v where aux (forward activation) > 0, else 0
 };
 
 // Operand precision of a layer's GEMM.
@@ -59,6 +61,7 @@ struct ConvArgs {
     int nphase, ncog;        // phases, output-channel groups
     int hs_exp;              // EP_INDEX: 1 = thresholds are ln(t_k), else t_k with ReLU
     int Hc, Wc;              // EP_RGB crop size
+    int kk, pad;             // LD_RGB kernel size and padding
 };
 
 }  // namespace lic

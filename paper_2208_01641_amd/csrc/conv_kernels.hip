@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
     static_assert(KSPLIT == 1 || KSPLIT == WAVES, "split-K blocks share one tile");
     static_assert(KSPLIT == 1 || EP != EP_RGB, "no split-K for the RGB output layer");
+    static_assert(EP != EP_MASK || DT == DT_F32, "gradients are FP32");
     constexpr int PIXW = WAVES / KSPLIT;           // waves with distinct pixel groups
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
@@ -138,8 +139,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     auto loadB = [&](int t, int kc, Frag (&B)[NT]) {
         if constexpr (LD == LD_RGB) {
-            // 5x5 stride-2 taps over 3 channels flattened: k = (5u + v) * 3 + c, zero beyond 75.
+            // kk x kk taps over 3 NCHW channels flattened, k = (kk u + v) * 3 + c,
+            // zero beyond 3 kk^2 (g_a's first layer: kk = 5, stride 2, pad 2)
             const float* in = static_cast<const float*>(a.in);
+            const int kk = a.kk, kn = 3 * a.kk * a.kk;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 Frag v;
@@ -147,9 +150,9 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 for (int e = 0; e < KE; ++e) {
                     const int k = kc * KCH + kg * KE + e;
                     const int tap = k / 3, c = k - 3 * (k / 3);
-                    const int u = tap / 5, w = tap - 5 * (tap / 5);
-                    const int iy = gy[nt] * 2 + u - 2, ix = gx[nt] * 2 + w - 2;
-                    const bool ok = pv[nt] && k < 75 && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                    const int u = tap / kk, w = tap - kk * (tap / kk);
+                    const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
+                    const bool ok = pv[nt] && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
                     float val = 0.0f;
                     if (ok) val = in[(((long)img[nt] * 3 + c) * a.Hin + iy) * a.Win + ix];
                     v[e] = (Elem)val;
@@ -380,26 +383,45 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 if (vout) *reinterpret_cast<f4*>(vout + obase[nt] + c) = y;
             }
     } else if constexpr (EP == EP_RGB) {
-        // rows r = 3 * (2 py + px) + c of the single m-tile are the four
-        // sub-pixel phases of the 3 output channels
-        static_assert(MT == 1, "EP_RGB uses one m-tile");
+        // rows r = 3 (S py + px) + c are the S x S sub-pixel phases of the 3
+        // output channels of a stride-S transposed convolution (S = s_out)
         float* out = static_cast<float*>(a.out);
         float* pre = static_cast<float*>(a.aux);
+        const int S = a.s_out, nrow = 3 * a.s_out * a.s_out;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            if (!pv[nt]) continue;
+        for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int r = kg * 4 + i;
-                if (r >= 12) continue;
-                const int q = r / 3, c = r - 3 * (r / 3);
-                const int y = gy[nt] * 2 + (q >> 1), x = gx[nt] * 2 + (q & 1);
-                const float v = acc[0][nt][i];
-                if (pre) pre[(((long)img[nt] * 3 + c) * a.Hout + y) * a.Wout + x] = v;
-                if (y < a.Hc && x < a.Wc)
-                    out[(((long)img[nt] * 3 + c) * a.Hc + y) * a.Wc + x] = fminf(fmaxf(v, 0.0f), 1.0f);
+            for (int nt = 0; nt < NT; ++nt) {
+                if (!pv[nt]) continue;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int r = mt * 16 + kg * 4 + i;
+                    if (r >= nrow) continue;
+                    const int q = r / 3, c = r - 3 * (r / 3);
+                    const int py = q / S, px = q - S * (q / S);
+                    const int y = gy[nt] * S + py, x = gx[nt] * S + px;
+                    const float v = acc[mt][nt][i];
+                    if (pre) pre[(((long)img[nt] * 3 + c) * a.Hout + y) * a.Wout + x] = v;
+                    if (out && y < a.Hc && x < a.Wc)
+                        out[(((long)img[nt] * 3 + c) * a.Hc + y) * a.Wc + x] = fminf(fmaxf(v, 0.0f), 1.0f);
+                }
             }
-        }
+    } else if constexpr (EP == EP_MASK) {
+        // ReLU backward: the gradient passes where the forward activation
+        // (aux, same layout as out) was positive
+        const float* mask = static_cast<const float*>(a.aux);
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int c = co0 + mt * 16 + kg * 4;
+                if (!(pv[nt] && c < a.Co)) continue;
+                const f4 m = *reinterpret_cast<const f4*>(mask + obase[nt] + c);
+                f4 y = acc[mt][nt];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) y[i] = m[i] > 0.0f ? y[i] : 0.0f;
+                *reinterpret_cast<f4*>(static_cast<float*>(a.out) + obase[nt] + c) = y;
+            }
     }
 }
 
@@ -459,6 +481,13 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    // distilled synthesis network (64 hidden channels): forward in FP32 or
+    // bf16 operands, input gradients (ReLU-masked) in FP32
+    LIC_K2(TAG_DT1, 192, LD_I8, EP_RELU), LIC_K2(TAG_DT1, 320, LD_I8, EP_RELU),
+    LIC_K2B(TAG_DT1, 192, LD_I8, EP_RELU), LIC_K2B(TAG_DT1, 320, LD_I8, EP_RELU),
+    LIC_K2(TAG_DT2, 64, LD_F32, EP_RELU), LIC_K2B(TAG_DT2, 64, LD_F32, EP_RELU),
+    LIC_K(TAG_DT3, 64, 3, 4, 4, LD_F32, EP_RGB), LIC_KB(TAG_DT3, 64, 3, 4, 4, LD_F32, EP_RGB),
+    LIC_K2(TAG_DB2, 64, LD_F32, EP_MASK), LIC_K2(TAG_DB3, 192, LD_RGB, EP_MASK),
 };
 
 bool kernel_available(const KernelKey& k)

@@ -2,6 +2,8 @@
 #pragma once
 #include <hip/hip_runtime_api.h>
 
+#include <string>
+
 #include "conv_args.h"
 
 namespace lic {
@@ -20,5 +22,20 @@ struct KernelKey {
 
 bool kernel_available(const KernelKey& k);
 hipError_t launch_conv(const KernelKey& k, const ConvArgs& args, int nblocks, hipStream_t stream);
+
+// Kernel tags beyond the codec's layer ids: the distilled synthesis network
+// (forward layers, and the input gradients of its second and third layer).
+enum { TAG_DT1 = 32, TAG_DT2 = 33, TAG_DT3 = 34, TAG_DB2 = 35, TAG_DB3 = 36 };
+
+// What the tile policy needs to know of a packed layer.
+struct ConvShape {
+    int tag, ld, ep, dt, cin, cop, nphase;
+};
+
+// Picks the tile configuration (split-K for small grids) from policy_pixels
+// (the pixel grid of one image, so that results do not depend on the batch),
+// sets a.ncog and launches over the a.n x a.Hg x a.Wg grid.  Returns a
+// lic_status; *errp names the failure.
+int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp);
 
 }  // namespace lic

@@ -6,6 +6,7 @@
 #include <algorithm>
 
 #include "codec.h"
+#include "packing.h"
 
 namespace lic {
 
@@ -257,116 +258,37 @@ int Codec::build_layers(const ParamMap& P)
         if (sp.ld == LD_RGB && ci != 3) { err = "ga0 must take 3 channels"; return LIC_E_MODEL; }
         if (!L.rows && co % 16 != 0) { err = std::string("channels must be multiples of 16: ") + sp.name; return LIC_E_MODEL; }
         if (L.rows && co != 3) { err = "gs3 must produce 3 channels"; return LIC_E_MODEL; }
-        // weight accessor in PyTorch layout
-        auto W = [&](int o, int c, int u, int v) -> double {
-            return sp.deconv ? w[(((size_t)c * co + o) * k + u) * k + v] : w[(((size_t)o * ci + c) * k + u) * k + v];
-        };
-
-        // phases and taps
-        std::vector<PhaseDesc> ph;
-        std::vector<std::vector<float>> packed;
-        const int p = k / 2;
-        if (sp.ld == LD_RGB) {
-            PhaseDesc d{};
-            d.ntaps = 1;
-            ph.push_back(d);
-            std::vector<float> wp((size_t)L.cop * krgb, 0.0f);
-            for (int o = 0; o < co; ++o)
-                for (int u = 0; u < 5; ++u)
-                    for (int v = 0; v < 5; ++v)
-                        for (int c = 0; c < 3; ++c) wp[(size_t)o * krgb + (u * 5 + v) * 3 + c] = (float)W(o, c, u, v);
-            packed.push_back(std::move(wp));
-        } else if (!sp.deconv) {
-            PhaseDesc d{};
-            d.ntaps = k * k;
-            std::vector<float> wp((size_t)k * k * L.cop * ci, 0.0f);
-            for (int u = 0; u < k; ++u)
-                for (int v = 0; v < k; ++v) {
-                    const int t = u * k + v;
-                    d.dy[t] = (int8_t)(u - p);
-                    d.dx[t] = (int8_t)(v - p);
-                    for (int o = 0; o < co; ++o)
-                        for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + o) * ci + c] = (float)W(o, c, u, v);
-                }
-            ph.push_back(d);
-            packed.push_back(std::move(wp));
-        } else if (!L.rows) {
-            // stride-2 transposed conv: output (2a + py, 2b + px) gathers taps u
-            // with (py + p - u) even from input row a + (py + p - u) / 2
-            for (int py = 0; py < 2; ++py)
-                for (int px = 0; px < 2; ++px) {
-                    PhaseDesc d{};
-                    d.oy = py;
-                    d.ox = px;
-                    std::vector<int> us, vs;
-                    for (int u = 0; u < k; ++u) if (((py + p - u) & 1) == 0) us.push_back(u);
-                    for (int v = 0; v < k; ++v) if (((px + p - v) & 1) == 0) vs.push_back(v);
-                    d.ntaps = (int)(us.size() * vs.size());
-                    std::vector<float> wp((size_t)d.ntaps * L.cop * ci, 0.0f);
-                    int t = 0;
-                    for (int u : us)
-                        for (int v : vs) {
-                            d.dy[t] = (int8_t)((py + p - u) / 2);
-                            d.dx[t] = (int8_t)((px + p - v) / 2);
-                            for (int o = 0; o < co; ++o)
-                                for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + o) * ci + c] = (float)W(o, c, u, v);
-                            ++t;
-                        }
-                    ph.push_back(d);
-                    packed.push_back(std::move(wp));
-                }
-        } else {
-            // transposed conv to 3 channels: all four phases as 12 GEMM rows
-            // r = 3 (2 py + px) + o over a 3x3 input neighbourhood
-            PhaseDesc d{};
-            d.ntaps = 9;
-            std::vector<float> wp((size_t)9 * L.cop * ci, 0.0f);
-            for (int dy = -1; dy <= 1; ++dy)
-                for (int dx = -1; dx <= 1; ++dx) {
-                    const int t = (dy + 1) * 3 + (dx + 1);
-                    d.dy[t] = (int8_t)dy;
-                    d.dx[t] = (int8_t)dx;
-                    for (int py = 0; py < 2; ++py)
-                        for (int px = 0; px < 2; ++px) {
-                            const int u = py + p - 2 * dy, v = px + p - 2 * dx;
-                            if (u < 0 || u >= k || v < 0 || v >= k) continue;
-                            for (int o = 0; o < 3; ++o) {
-                                const int r = 3 * (2 * py + px) + o;
-                                for (int c = 0; c < ci; ++c) wp[((size_t)t * L.cop + r) * ci + c] = (float)W(o, c, u, v);
-                            }
-                        }
-                }
-            ph.push_back(d);
-            packed.push_back(std::move(wp));
-        }
+        // packed GEMM operands as index maps into the PyTorch-layout weights
+        PackMap pm;
+        if (sp.ld == LD_RGB) pm = pack_map(PK_IMG, 3, co, k, 2, k / 2, false, krgb);
+        else if (!sp.deconv) pm = pack_map(PK_CONV, ci, co, k, 1, k / 2, false);
+        else if (!L.rows) pm = pack_map(PK_DECONV, ci, co, k, 2, k / 2, true);
+        else pm = pack_map(PK_ROWS, ci, co, k, 2, k / 2, true);
+        if (pm.cin != L.cin || pm.cop != L.cop) { err = std::string("packing mismatch in ") + sp.name; return LIC_E_MODEL; }
+        std::vector<PhaseDesc> ph = pm.ph;
         L.nphase = (int)ph.size();
 
-        size_t total = 0;
-        for (auto& v : packed) total += v.size();
+        const size_t total = pm.idx.size();
         const size_t esz = L.dt == DT_BF16 ? 2 : 4;
         L.d_w = (uint8_t*)dev_alloc(total * esz);
         L.d_ph = (PhaseDesc*)dev_alloc(ph.size() * sizeof(PhaseDesc));
         L.d_bias = (float*)dev_alloc(L.cop * sizeof(float));
         if (!L.d_w || !L.d_ph || !L.d_bias) { err = "device allocation failed"; return LIC_E_NOMEM; }
-        size_t off = 0;
-        for (size_t i = 0; i < packed.size(); ++i) {
-            if (L.dt == DT_BF16) {
-                std::vector<uint16_t> hb(packed[i].size());
-                for (size_t j = 0; j < hb.size(); ++j) hb[j] = bf16_rne(packed[i][j]);
-                HIP_TRY(hipMemcpy(L.d_w + off * esz, hb.data(), hb.size() * esz, hipMemcpyHostToDevice));
-            } else {
-                HIP_TRY(hipMemcpy(L.d_w + off * esz, packed[i].data(), packed[i].size() * esz, hipMemcpyHostToDevice));
-            }
-            ph[i].w = L.d_w + off * esz;
-            off += packed[i].size();
+        std::vector<float> wp(total);
+        for (size_t j = 0; j < total; ++j) wp[j] = pm.idx[j] < 0 ? 0.0f : (float)w[pm.idx[j]];
+        if (L.dt == DT_BF16) {
+            std::vector<uint16_t> hb(total);
+            for (size_t j = 0; j < total; ++j) hb[j] = bf16_rne(wp[j]);
+            HIP_TRY(hipMemcpy(L.d_w, hb.data(), total * esz, hipMemcpyHostToDevice));
+        } else {
+            HIP_TRY(hipMemcpy(L.d_w, wp.data(), total * esz, hipMemcpyHostToDevice));
         }
+        for (size_t i = 0; i < ph.size(); ++i) ph[i].w = L.d_w + pm.off[i] * esz;
         HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
         L.host_ph = ph;
         std::vector<float> bias(L.cop, 0.0f);
-        for (int r = 0; r < L.cop; ++r) {
-            if (L.rows) { if (r < 12) bias[r] = (float)b[r % 3]; }
-            else if (r < co) bias[r] = (float)b[r];
-        }
+        for (int r = 0; r < L.cop; ++r)
+            if (pm.bias_idx[r] >= 0) bias[r] = (float)b[pm.bias_idx[r]];
         HIP_TRY(hipMemcpy(L.d_bias, bias.data(), L.cop * sizeof(float), hipMemcpyHostToDevice));
 
         if (sp.ep == EP_GDN || sp.ep == EP_IGDN) {
@@ -448,20 +370,29 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.hs_exp = hs_exp;
     a.Hc = d.H;
     a.Wc = d.W;
+    a.kk = L.k;
+    a.pad = L.k / 2;
 
-    KernelKey key{id, L.cin, 0, 0, 0, 1, L.ld, L.ep, L.dt};
-    const long pixels = (long)n * g.Hg * g.Wg;
+    const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase};
+    return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp);
+}
+
+int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp)
+{
+    KernelKey key{L.tag, L.cin, 0, 0, 0, 1, L.ld, L.ep, L.dt};
+    const long pixels = (long)a.n * a.Hg * a.Wg;
     if (L.ep == EP_GDN || L.ep == EP_IGDN) {
-        key.mt = L.co / 16;
+        key.mt = L.cop / 16;
         key.nt = key.mt <= 8 ? 2 : 1;
         key.waves = 4;
         a.ncog = 1;
         // fewer than one wave per SIMD (1024 on the chip) from the pixel
         // grid of one image: split K over the 4 waves of a block instead
-        const long img_waves = ((long)g.Hg * g.Wg + 16 * key.nt - 1) / (16 * key.nt) * L.nphase;
+        const long img_waves = (policy_pixels + 16 * key.nt - 1) / (16 * key.nt) * L.nphase;
         if (L.ld != LD_RGB && img_waves < 1024) key.ksplit = 4;
     } else if (L.ep == EP_RGB) {
-        key.mt = 1;
+        // every row of the transposed convolution to 3 channels in one wave
+        key.mt = L.cop / 16;
         key.nt = 4;
         key.waves = 4;
         a.ncog = 1;
@@ -471,8 +402,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
         // only the tiniest layers fall back to 16 x 16 tiles (split 8).  The
         // choice depends on the per-image size only, so a frame gives the
         // same bits alone or in a batch (split-K changes the summation order).
-        const long img_pixels = (long)g.Hg * g.Wg;
-        const long tiles_big = ((img_pixels + 31) / 32) * L.nphase * (L.cop / 64);
+        const long tiles_big = ((policy_pixels + 31) / 32) * L.nphase * (L.cop / 64);
         key.mt = 4; key.nt = 2;
         if (L.cop % 64 != 0 || tiles_big < 32) {
             key.mt = 1; key.nt = 1; key.waves = 8; key.ksplit = 8;
@@ -490,6 +420,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     const long nblocks = tiles * L.nphase * a.ncog;
     if (nblocks <= 0) return LIC_OK;
     if (nblocks > (1L << 30)) { *errp = "launch too large"; return LIC_E_BUDGET; }
+    if (!kernel_available(key)) { *errp = "no kernel instantiated for this layer shape"; return LIC_E_ARG; }
     hipError_t e = launch_conv(key, a, (int)nblocks, s);
     if (e != hipSuccess) {
         *errp = std::string("kernel launch failed: ") + hipGetErrorString(e);
