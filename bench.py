@@ -11,8 +11,8 @@ per frame); the input frames are resident in device memory before timing.
 
 The headline line is the FP32 form at N=128, M=192.  Unless --no-variants
 is given, the same JSON line also carries the comparison runs ("variants"):
-the unpipelined per-frame form (one frame in flight), the BF16 form at
-720p, and the FP32 / BF16 forms of the 1080p N=192 M=320 batch-4 workload,
+the unpipelined per-frame form (one frame in flight), the BF16 and e4m3 forms at
+720p, and the FP32 / BF16 / e4m3 forms of the 1080p N=192 M=320 batch-4 workload,
 each with frames/s, p50/p99 latency, PSNR and bits per pixel, and the
 serving loop (16 mixed-resolution streams, Poisson arrivals, BF16).
 
@@ -30,7 +30,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "720p hyperprior enc+dec frames/s + p99 ms; BF16/FP8 vs FP32 at fixed PSNR"
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0}   # MI355X dense matrix peaks
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_01641_amd", "csrc", "conv_kernels.hip")
 LAYERS = ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3")
@@ -235,6 +235,103 @@ def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7):
             "e2e_p50_ms": pct(lat_e2e, 50), "e2e_p99_ms": pct(lat_e2e, 99)}
 
 
+def run_distilled(*, pairs, steps, threads, batch=32, holdout=256, deploy_frames=120, seed=0):
+    """Distilled g_s: pairs (y_hat, x_hat) of 256x256 crops from the FP32
+    N=128 M=192 decoder, GPU training (AdamW, batch 32), judge calibration
+    on held-out crops, then 720p decoding with the full and the distilled
+    g_s (frames/s, p99, PSNR gap)."""
+    import numpy as np
+    import torch
+
+    import synth
+    from paper_2208_01641_amd import Codec, Distill
+    from paper_2208_01641_amd import distill_train as dtr
+
+    N, M, F = 128, 192, 64
+    P = synth.model_params(1, N, M)
+    blob = synth.weight_blob(P, 1, N, M)
+    teacher = Codec(blob, kind=1, N=N, M=M, hs_out=1, precision=0, y_slices=1, entropy_threads=2, max_in_flight=1,
+                    max_h=256, max_w=256)
+    total = pairs + holdout
+    imgs = torch.empty((total, 3, 256, 256), device="cuda")
+    for i in range(total):                 # one generator stream per crop
+        imgs[i] = synth.frames_sinusoid_torch(256, 256, [0], stream=10 ** 6 + i, device="cuda")[0]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sym, rec = dtr.build_pairs(teacher, imgs)
+    torch.cuda.synchronize()
+    t_pairs = time.perf_counter() - t0
+    teacher.close()
+    net = Distill(synth.distill_params(M, F), M, F, max_batch=batch, max_hy=16, max_wy=16)
+    dtr.train(net, sym[:pairs], rec[:pairs], 5, batch, seed=seed + 1)          # warm-up (discarded state below)
+    net.set(0, synth_flat(synth.distill_params(M, F)))
+    net.set(1, np.zeros(net.n_params, np.float32))
+    net.set(2, np.zeros(net.n_params, np.float32))
+    net.step_count = 0
+    t0 = time.perf_counter()
+    losses = dtr.train(net, sym[:pairs], rec[:pairs], steps, batch, seed=seed)
+    t_train = time.perf_counter() - t0
+    fid, gap = dtr.evaluate(net, sym[pairs:], rec[pairs:], imgs[pairs:])
+    T = dtr.judge_threshold(fid, gap)
+    params = net.get(0)
+    net.close()
+    del sym, rec, imgs
+    torch.cuda.empty_cache()
+
+    # deployment: decode 720p frames with the full and the distilled g_s
+    H, W = 720, 1280
+    frames = synth.frames_sinusoid_torch(H, W, range(deploy_frames), device="cuda")
+    out = {}
+    for name, mode, prec in (("full_fp32", 0, 0), ("distilled_fp32", 1, 0), ("distilled_bf16", 1, 1),
+                             ("distilled_judged_fp32", 2, 0)):
+        c = Codec(blob, kind=1, N=N, M=M, hs_out=1, precision=0 if mode == 0 else prec, y_slices=8,
+                  entropy_threads=threads, max_in_flight=6, max_h=H, max_w=W, gs_mode=mode)
+        if mode:
+            c.load_distilled(params, judge_psnr_db=T if math.isfinite(T) else 1e9, judge_every=30)
+        bits = c.encode(frames) if mode == 0 or "enc" not in out else out["enc"]
+        out.setdefault("enc", bits)
+        xr = torch.empty_like(frames)
+        c.decode(bits[:8], xr[:8])                     # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.decode(bits, xr)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        lat = c.latencies_ms()
+        mse = torch.mean((xr - frames) ** 2, dim=(1, 2, 3))
+        r = {"decode_fps": deploy_frames / dt, "p50_ms": float(np.percentile(lat, 50)),
+             "p99_ms": float(np.percentile(lat, 99)), "psnr_db": float(torch.mean(10 * torch.log10(1.0 / mse)))}
+        if mode:
+            st = c.stats()
+            r.update(gs_judged=st["gs_judged"], gs_fallback=st["gs_fallback"])
+            r["psnr_vs_full_db"] = float(torch.mean(10 * torch.log10(1.0 / torch.mean((xr - out["full_xr"]) ** 2,
+                                                                                     dim=(1, 2, 3)))))
+        else:
+            out["full_xr"] = xr
+        out[name] = _round(r)
+        c.close()
+    full = out.pop("full_xr")
+    del full, frames
+    out.pop("enc")
+    for k in ("distilled_fp32", "distilled_bf16", "distilled_judged_fp32"):
+        out[k]["gap_db_vs_full"] = round(out["full_fp32"]["psnr_db"] - out[k]["psnr_db"], 4)
+    flops_per_sample = 3 * 2 * 0.2338e9           # forward + input and weight gradients
+    return {
+        "pairs": pairs, "steps": steps, "batch": batch, "pairs_s": round(t_pairs, 3), "train_s": round(t_train, 3),
+        "train_samples_per_s": round(steps * batch / t_train, 1),
+        "train_tflops": round(steps * batch * flops_per_sample / t_train / 1e12, 2),
+        "loss_first": float(losses[:10].mean()), "loss_last": float(losses[-100:].mean()),
+        "holdout_fidelity_db": round(float(np.mean(fid)), 3), "holdout_gap_db": round(float(np.mean(gap)), 4),
+        "judge_threshold_db": T if math.isfinite(T) else None,
+        "deploy_720p": out,
+    }
+
+
+def synth_flat(P):
+    from paper_2208_01641_amd.distill import flatten
+    return flatten(P)
+
+
 def _round(d, nd=3):
     return {k: (round(v, nd) if isinstance(v, float) else v) for k, v in d.items()}
 
@@ -246,7 +343,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=30, help="untimed frames first")
     ap.add_argument("--height", type=int, default=720)
     ap.add_argument("--width", type=int, default=1280)
-    ap.add_argument("--precision", choices=["fp32", "bf16"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "bf16", "fp8"], default="fp32")
     ap.add_argument("--threads", type=int, default=0, help="entropy worker threads (0: min(16, cores))")
     ap.add_argument("--inflight", type=int, default=6, help="tasks in flight (pooled slots)")
     ap.add_argument("--slices", type=int, default=8, help="rANS row slices of y")
@@ -255,6 +352,10 @@ def main():
     ap.add_argument("--all-layers", action="store_true", help="time every layer (per-layer breakdown)")
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--distill-pairs", type=int, default=2000,
+                    help="distilled g_s variant: training pairs (0 skips the variant)")
+    ap.add_argument("--distill-steps", type=int, default=1500, help="distilled g_s variant: AdamW steps")
+    ap.add_argument("--distill-only", action="store_true", help="run only the distilled g_s variant")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="also run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -267,7 +368,12 @@ def main():
     import torch
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     threads = args.threads or min(16, os.cpu_count() or 1)
-    prec = 1 if args.precision == "bf16" else 0
+    if args.distill_only:
+        print(json.dumps({"distilled_gs": run_distilled(pairs=args.distill_pairs, steps=args.distill_steps,
+                                                        threads=threads)}), flush=True)
+        return
+    prec = {"fp32": 0, "bf16": 1, "fp8": 2}[args.precision]
+    dtype = {0: "f32", 1: "bf16", 2: "fp8"}[prec]
     H, W, K, Wm = args.height, args.width, args.steps, args.warmup
     N, M = 128, 192
     timed = list(LAYERS) if args.all_layers else ["GA1", "GS2"]
@@ -278,7 +384,7 @@ def main():
 
     per_layer = main_res["layers"]
     dom = max(per_layer, key=lambda L: per_layer[L]["avg_us"] * per_layer[L]["launches"])
-    peak = PEAK_TFLOPS["bf16" if prec else "f32"]
+    peak = PEAK_TFLOPS[dtype]
     ach = per_layer[dom]["tflops"]
     roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4), "traffic": traffic_for(dom) if not prec else None,
@@ -296,7 +402,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "bf16" if prec else "f32",
+        "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"scale-hyperprior N={N} M={M} {args.precision.upper()} encode chained into decode, "
                                f"3x{H}x{W} frames (32 moving sinusoids + noise), pipelined",
@@ -325,15 +431,24 @@ def main():
         var["bf16_720p"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
         var["bf16_720p"]["d_psnr_db_vs_fp32"] = round(r["psnr_db"] - main_res["psnr_db"], 4)
         var["bf16_720p"]["d_bpp_vs_fp32"] = round(r["bpp"] - main_res["bpp"], 5)
+        r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=2, batch=1, steps=300, warmup=30,
+                                  inflight=args.inflight, **common)
+        var["fp8_720p"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        var["fp8_720p"]["d_psnr_db_vs_fp32"] = round(r["psnr_db"] - main_res["psnr_db"], 4)
+        var["fp8_720p"]["d_bpp_vs_fp32"] = round(r["bpp"] - main_res["bpp"], 5)
         big = {}
-        for name, p in (("fp32", 0), ("bf16", 1)):
+        for name, p in (("fp32", 0), ("bf16", 1), ("fp8", 2)):
             r, _, _, _ = run_workload(H=1080, W=1920, N=192, M=320, precision=p, batch=4, steps=40, warmup=8,
                                       inflight=3, **common)
             big[name] = r
             var[f"{name}_1080p_n192_m320_batch4"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
         var["bf16_1080p_n192_m320_batch4"]["d_psnr_db_vs_fp32"] = round(big["bf16"]["psnr_db"] - big["fp32"]["psnr_db"], 4)
         var["bf16_1080p_n192_m320_batch4"]["d_bpp_vs_fp32"] = round(big["bf16"]["bpp"] - big["fp32"]["bpp"], 5)
+        var["fp8_1080p_n192_m320_batch4"]["d_psnr_db_vs_fp32"] = round(big["fp8"]["psnr_db"] - big["fp32"]["psnr_db"], 4)
+        var["fp8_1080p_n192_m320_batch4"]["d_bpp_vs_fp32"] = round(big["fp8"]["bpp"] - big["fp32"]["bpp"], 5)
         var["serving_16_streams_bf16"] = _round(run_serving(precision=1, threads=threads))
+        if args.distill_pairs > 0:
+            var["distilled_gs"] = run_distilled(pairs=args.distill_pairs, steps=args.distill_steps, threads=threads)
         res["variants"] = var
 
     if not args.no_cpu_baseline:

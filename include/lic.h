@@ -50,7 +50,7 @@ typedef enum {
 } lic_status;
 
 enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1 };
-enum { LIC_PREC_FP32 = 0, LIC_PREC_BF16 = 1 };
+enum { LIC_PREC_FP32 = 0, LIC_PREC_BF16 = 1, LIC_PREC_FP8 = 2 };
 enum { LIC_HS_RELU = 0, LIC_HS_EXP = 1 };
 
 /* Creation parameters.  Fill with codec_default_config() first. */
@@ -58,12 +58,16 @@ typedef struct {
     uint32_t struct_size;      /* sizeof(codec_config), for ABI versioning           */
     int32_t  kind;             /* LIC_KIND_*: factorized prior [1] or hyperprior [2] */
     int32_t  N, M;             /* transform / latent channels (128/192 or 192/320)   */
-    int32_t  precision;        /* LIC_PREC_FP32, or LIC_PREC_BF16: g_a / g_s GEMM    */
-                               /* operands and their activations in bf16 (FP32    */
-                               /* accumulation, FP32 GDN/IGDN); h_a, h_s, the     */
-                               /* quantisers and the scale index stay FP32        */
+    int32_t  precision;        /* LIC_PREC_FP32, _BF16 or _FP8: g_a / g_s GEMM       */
+                               /* operands and their activations in bf16, or in OCP  */
+                               /* e4m3 with per-output-channel FP32 weight scales    */
+                               /* and a fixed activation scale (FP32 accumulation,   */
+                               /* FP32 GDN/IGDN); h_a, h_s, the quantisers and the   */
+                               /* scale index stay FP32                              */
     int32_t  hs_out;           /* output activation of h_s: LIC_HS_EXP or _RELU      */
-    int32_t  gs_mode;          /* 0: full synthesis transform                        */
+    int32_t  gs_mode;          /* 0: full synthesis transform g_s; 1: distilled g_s  */
+                               /* (codec_load_distilled); 2: distilled g_s with a    */
+                               /* sampled judge that falls back to the full g_s      */
     int32_t  y_slices;         /* S >= 1 independent rANS streams for y (row bands)  */
     int32_t  entropy_threads;  /* CPU entropy worker threads (paper: 3 and 10)       */
     int32_t  zero_copy;        /* 1: kernels read/write mapped pinned host slots;    */
@@ -193,6 +197,17 @@ enum {
     LIC_GS0, LIC_GS1, LIC_GS2, LIC_GS3,
     LIC_NUM_LAYERS
 };
+/* Loads the distilled synthesis transform used by the decoder when gs_mode
+ * is 1 or 2 (parameters as for lic_distill_create, M of this codec, F = 64,
+ * host array, copied; GEMM operands in the codec's precision).  With gs_mode
+ * 2, the task holding every judge_every-th decoded frame also decodes its
+ * first frame with the full g_s; if PSNR(full, distilled) < judge_psnr_db
+ * the codec switches to the full g_s for good (the judged task included).
+ * codec_get_stats reports gs_judged, gs_judge_last_db and gs_fallback.  Call
+ * while no decode is in flight. */
+int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float judge_psnr_db,
+                         int judge_every);
+
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
                     const void* in, void* out, void* aux);
 

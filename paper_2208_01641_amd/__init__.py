@@ -5,3 +5,4 @@ Python side = argument marshalling over the C ABI of liblic.so
 """
 from .codec import Codec, LicError, rans_decode, rans_encode, fnv1a  # noqa: F401
 from ._lib import LAYERS, LAYER_ID  # noqa: F401
+from .distill import Distill  # noqa: F401,E402

@@ -39,13 +39,14 @@ class Codec:
     def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1, precision: int = 0,
                  y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 1, max_in_flight: int = 6,
                  max_h: int = 1088, max_w: int = 1920, max_batch: int = 1, hbm_budget_bytes: int = 0,
-                 device: int = 0, use_graphs: int = 1):
+                 device: int = 0, use_graphs: int = 1, gs_mode: int = 0):
         cfg = _lib.CodecConfig()
         lib.codec_default_config(ctypes.byref(cfg))
         cfg.kind, cfg.N, cfg.M, cfg.hs_out, cfg.precision = kind, N, M, hs_out, precision
         cfg.y_slices, cfg.entropy_threads, cfg.zero_copy = y_slices, entropy_threads, zero_copy
         cfg.max_in_flight, cfg.max_h, cfg.max_w, cfg.max_batch = max_in_flight, max_h, max_w, max_batch
         cfg.hbm_budget_bytes, cfg.hip_device, cfg.use_graphs = hbm_budget_bytes, device, use_graphs
+        cfg.gs_mode = gs_mode
         self.cfg = cfg
         self.kind, self.N, self.M, self.S, self.precision = kind, N, M, y_slices, precision
         self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
@@ -123,6 +124,15 @@ class Codec:
             res.append(bits[off:off + ln].tobytes())
             off += ln
         return res
+
+    def load_distilled(self, params, judge_psnr_db: float = 0.0, judge_every: int = 30):
+        """Distilled g_s for gs_mode 1 / 2: params is the flat float32 vector
+        (or the dict) of paper_2208_01641_amd.distill."""
+        from .distill import flatten
+        if isinstance(params, dict):
+            params = flatten(params, self.M, 64)
+        v = np.ascontiguousarray(params, np.float32)
+        self._check(lib.codec_load_distilled(self._h, v.ctypes.data, v.size, judge_psnr_db, judge_every))
 
     def run_layer(self, layer, n: int, H: int, W: int, inp, out, aux=None):
         lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)

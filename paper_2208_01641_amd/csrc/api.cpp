@@ -84,9 +84,12 @@ int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, cod
     if (!cfg || !blob || !out) { g_create_error = "null argument"; return LIC_E_ARG; }
     if (cfg->struct_size != sizeof(codec_config)) { g_create_error = "codec_config size mismatch"; return LIC_E_ARG; }
     if (!supported_shape(cfg->kind, cfg->N, cfg->M)) { g_create_error = "unsupported kind/N/M"; return LIC_E_ARG; }
-    if (cfg->precision != LIC_PREC_FP32 && cfg->precision != LIC_PREC_BF16) { g_create_error = "unsupported precision"; return LIC_E_ARG; }
+    if (cfg->precision != LIC_PREC_FP32 && cfg->precision != LIC_PREC_BF16 && cfg->precision != LIC_PREC_FP8) {
+        g_create_error = "unsupported precision";
+        return LIC_E_ARG;
+    }
     if (cfg->hs_out != LIC_HS_EXP && cfg->hs_out != LIC_HS_RELU) { g_create_error = "bad hs_out"; return LIC_E_ARG; }
-    if (cfg->gs_mode != 0) { g_create_error = "unsupported gs_mode"; return LIC_E_ARG; }
+    if (cfg->gs_mode < 0 || cfg->gs_mode > 2) { g_create_error = "gs_mode must be 0, 1 or 2"; return LIC_E_ARG; }
     if (cfg->y_slices < 1 || cfg->y_slices > lic::kMaxSlices) { g_create_error = "y_slices must be 1..64"; return LIC_E_ARG; }
     if (cfg->entropy_threads < 1 || cfg->entropy_threads > 256) { g_create_error = "bad entropy_threads"; return LIC_E_ARG; }
     if (cfg->max_in_flight < 1 || cfg->max_in_flight > 64) { g_create_error = "max_in_flight must be 1..64"; return LIC_E_ARG; }
@@ -253,12 +256,23 @@ int codec_get_stats(const codec_t* c, char* buf, size_t cap)
     int n = snprintf(buf, cap,
                      "{\"frames\": %d, \"wall_s\": %.6f, \"fps\": %.3f, \"p50_ms\": %.4f, \"p99_ms\": %.4f, "
                      "\"gpu_busy_s\": [%.6f, %.6f, %.6f], \"cpu_busy_s\": %.6f, \"device_bytes\": %zu, "
-                     "\"alloc_events\": %ld, \"entropy_threads\": %d, \"max_in_flight\": %d, \"zero_copy\": %d}",
+                     "\"alloc_events\": %ld, \"entropy_threads\": %d, \"max_in_flight\": %d, \"zero_copy\": %d, "
+                     "\"gs_mode\": %d, \"gs_judged\": %ld, \"gs_judge_last_db\": %.4f, \"gs_fallback\": %d}",
                      c->last_frames, c->last_wall_s, fps, pct(0.50), pct(0.99), c->gpu[0].busy_s, c->gpu[1].busy_s,
                      c->gpu[2].busy_s, c->cpu_busy_us.load() * 1e-6, c->dev_bytes, c->alloc_events.load(),
-                     c->cfg.entropy_threads, c->cfg.max_in_flight, c->cfg.zero_copy);
+                     c->cfg.entropy_threads, c->cfg.max_in_flight, c->cfg.zero_copy, c->cfg.gs_mode,
+                     c->gs_judged.load(), c->gs_judge_last_db, (int)c->gs_fallback.load());
     if (n < 0 || (size_t)n >= cap) return LIC_E_SMALLBUF;
     return n;
+}
+
+int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float judge_psnr_db, int judge_every)
+{
+    if (!c || !params) return LIC_E_ARG;
+    if (hipSetDevice(c->cfg.hip_device) != hipSuccess) return fail(c, LIC_E_HIP, "hipSetDevice");
+    const int rc = c->load_distilled(params, n_params, judge_psnr_db, judge_every);
+    if (rc != LIC_OK) return fail(c, rc, c->err);
+    return LIC_OK;
 }
 
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W, const void* in, void* out, void* aux)

@@ -17,6 +17,7 @@
 #include "../../include/lic.h"
 #include "conv_args.h"
 #include "entropy.h"
+#include "distill.h"
 #include "kernels.h"
 
 namespace lic {
@@ -34,11 +35,16 @@ struct LayerGPU {
     PhaseDesc* d_ph = nullptr;
     uint8_t* d_w = nullptr;            // packed weights (float or bf16)
     float* d_bias = nullptr;
+    float* d_rscale = nullptr;         // e4m3 form: per packed row, weight scale x input scale
     float* d_gamma = nullptr;
     float* d_beta = nullptr;
     const float* d_qmu = nullptr;      // EP_QUANT offsets
     const float* d_mu_in = nullptr;    // LD_I8 offsets
 };
+
+// e4m3 activations between layers hold kActQ x the value (|value| <= 56 fits)
+constexpr float kActQ = 8.0f;
+uint8_t e4m3_rne(float f);
 
 struct Geo {
     int Hin, Win, Hg, Wg, s_in, Hout, Wout, s_out;
@@ -78,6 +84,7 @@ struct Task {
     const float* xs[kMaxBatch] = {};   // input frame of each batch entry
     float* xhats[kMaxBatch] = {};      // output frame of each batch entry
     bool staged = false;               // request buffers copied in / out by the caller
+    bool judge = false;                // g_s stage: also run the full g_s on frame 0 and compare
     std::atomic<int> jobs_left{0};
     std::atomic<int> status{0};
     std::mutex err_m;
@@ -288,6 +295,19 @@ struct Codec {
 
     // serving (continuous batching over per-shape buckets)
     std::unique_ptr<Server> server;
+
+    // distilled synthesis transform (gs_mode 1, 2) and its sampled judge
+    std::unique_ptr<DistillNet> distill;
+    float judge_db = 0.0f;                   // fall back when PSNR(full, distilled) < judge_db
+    int judge_every = 30;                    // frames between judged frames
+    std::atomic<bool> gs_fallback{false};
+    std::atomic<long> gs_frames{0}, gs_judged{0};
+    double gs_judge_last_db = 0.0;
+    float* d_judge_img = nullptr;            // 3 x max_h x max_w
+    float* d_judge_part = nullptr;
+    float* h_judge = nullptr;                // pinned: the squared error of the last judge
+    int load_distilled(const float* params, size_t n, float judge_psnr_db, int every);
+    int gs_judge(Task* t, GpuStage& G, float* xo);
     int server_submit(Request* r, uint64_t* ticket);
     int server_poll(lic_result* out, int max, int timeout_us);
     void server_finish(Task* t);

@@ -30,6 +30,7 @@ enum Epilogue : int {
 enum DType : int {
     DT_F32 = 0,
     DT_BF16 = 1,
+    DT_FP8 = 2,      // OCP e4m3 operands with per-row FP32 scales (rscale)
 };
 
 // One phase of a layer.  A plain convolution has one phase; a stride-2
@@ -62,6 +63,8 @@ struct ConvArgs {
     int hs_exp;              // EP_INDEX: 1 = thresholds are ln(t_k), else t_k with ReLU
     int Hc, Wc;              // EP_RGB crop size
     int kk, pad;             // LD_RGB kernel size and padding
+    const float* rscale;     // DT_FP8: per packed row, weight scale x input scale
+    float out_q;             // DT_FP8: activations are stored as e4m3(out_q * value)
 };
 
 }  // namespace lic

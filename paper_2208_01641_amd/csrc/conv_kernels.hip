@@ -32,6 +32,7 @@ namespace lic {
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef int i32x8 __attribute__((ext_vector_type(8)));
 
 __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
 {
@@ -54,6 +55,28 @@ template <> struct Prec<DT_BF16> {
     using Elem = __bf16;
     static constexpr int KCH = 32, KE = 8;
 };
+//   DT_FP8 : v_mfma_scale_f32_16x16x128_f8f6f4 on OCP e4m3 operands (unit
+//            block scales), K walked over the flattened (tap, channel) axis in
+//            chunks of 128: lane group g takes 32 consecutive channels of one
+//            tap (channels per tap are a multiple of 32).  Weights carry a
+//            per-row FP32 scale and activations are stored as e4m3(q x) with
+//            a fixed per-layer q, both undone in the epilogue.
+template <> struct Prec<DT_FP8> {
+    using Frag = i32x8;
+    using Elem = uint8_t;
+    static constexpr int KCH = 128, KE = 32;
+};
+
+// e4m3 code of two floats in the low 16 bits, saturated to +-448 first
+__device__ __forceinline__ uint32_t e4m3x2(float lo, float hi)
+{
+    lo = fminf(fmaxf(lo, -448.0f), 448.0f);
+    hi = fminf(fmaxf(hi, -448.0f), 448.0f);
+    return (uint32_t)__builtin_amdgcn_cvt_pk_fp8_f32(lo, hi, 0, false) & 0xffffu;
+}
+
+// unit E8M0 block scale (2^0) of the scaled MFMA
+constexpr int kE8M0One = 127;
 
 // Blocks are dispatched round-robin over the 8 XCDs (block L goes to XCD
 // L % 8).  Give each XCD a contiguous range of logical tiles so that tiles
@@ -78,8 +101,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     using Frag = typename Prec<DT>::Frag;
     using Elem = typename Prec<DT>::Elem;
     constexpr int KCH = Prec<DT>::KCH, KE = Prec<DT>::KE;
-    constexpr int KC = CIN / KCH;
-    static_assert(CIN % KCH == 0, "whole K chunks");
+    constexpr int KC = DT == DT_FP8 ? 1 : CIN / KCH;
+    static_assert(DT == DT_FP8 ? CIN % 32 == 0 : CIN % KCH == 0, "whole K chunks");
     static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
     static_assert(KSPLIT == 1 || KSPLIT == WAVES, "split-K blocks share one tile");
     static_assert(KSPLIT == 1 || EP != EP_RGB, "no split-K for the RGB output layer");
@@ -126,7 +149,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         f4 b = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (kslot == 0) b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
+        if (DT != DT_FP8 && kslot == 0) b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = b;
     }
@@ -204,12 +227,82 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                     for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], B[nt][e], acc[mt][nt]);
-        } else {
+        } else if constexpr (DT == DT_BF16) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt)
                     acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], B[nt], acc[mt][nt], 0, 0, 0);
+        } else {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        A[mt], B[nt], acc[mt][nt], 0, 0, 0, kE8M0One, 0, kE8M0One);
+        }
+    };
+
+    // DT_FP8: chunk kc of the flattened (tap, channel) axis; this lane group
+    // takes channels c .. c + 31 of tap t (t >= ntaps: past the end, zeros)
+    auto loadA8 = [&](int kc, Frag (&A)[MT]) {
+        const int f = kc * KCH + kg * KE;
+        const int t = f / CIN, c = f - (f / CIN) * CIN;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            Frag v = {};
+            if (t < ntaps) v = *reinterpret_cast<const Frag*>(wbase + ((long)t * CoP + co0 + mt * 16 + l16) * CIN + c);
+            A[mt] = v;
+        }
+    };
+    auto pack4 = [](float v0, float v1, float v2, float v3) -> int {
+        return (int)(e4m3x2(v0, v1) | (e4m3x2(v2, v3) << 16));
+    };
+    auto loadB8 = [&](int kc, Frag (&B)[NT]) {
+        const int f = kc * KCH + kg * KE;
+        const int t = f / CIN, c = f - (f / CIN) * CIN;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            Frag v = {};
+            if constexpr (LD == LD_RGB) {
+                // flattened (tap, channel) pairs of the 3-channel NCHW input
+                const float* in = static_cast<const float*>(a.in);
+                const int kk = a.kk, kn = 3 * a.kk * a.kk;
+                float x[KE];
+#pragma unroll
+                for (int e = 0; e < KE; ++e) {
+                    const int k = c + e;
+                    const int tap = k / 3, ch = k - 3 * (k / 3);
+                    const int u = tap / kk, w = tap - kk * (tap / kk);
+                    const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
+                    const bool ok = pv[nt] && t < ntaps && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                    x[e] = ok ? in[(((long)img[nt] * 3 + ch) * a.Hin + iy) * a.Win + ix] : 0.0f;
+                }
+#pragma unroll
+                for (int q = 0; q < 8; ++q) v[q] = pack4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
+            } else if (t < ntaps) {
+                const int iy = gy[nt] * a.s_in + ph->dy[t], ix = gx[nt] * a.s_in + ph->dx[t];
+                const bool ok = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + c;
+                if (ok) {
+                    if constexpr (LD == LD_I8) {
+                        // y_hat = symbol + offset, rounded to e4m3 (exact for |y_hat| <= 16)
+                        const int8_t* src = static_cast<const int8_t*>(a.in) + off;
+                        const float* mu = a.mu_in + c;
+                        const uint4 u0 = *reinterpret_cast<const uint4*>(src);
+                        const uint4 u1 = *reinterpret_cast<const uint4*>(src + 16);
+                        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
+#pragma unroll
+                        for (int q = 0; q < 8; ++q)
+                            v[q] = pack4((float)(int8_t)(w[q]) + mu[4 * q], (float)(int8_t)(w[q] >> 8) + mu[4 * q + 1],
+                                         (float)(int8_t)(w[q] >> 16) + mu[4 * q + 2],
+                                         (float)(int8_t)(w[q] >> 24) + mu[4 * q + 3]);
+                    } else {
+                        v = *reinterpret_cast<const Frag*>(static_cast<const Elem*>(a.in) + off);
+                    }
+                }
+            }
+            B[nt] = v;
         }
     };
 
@@ -217,6 +310,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     auto store_act = [&](long idx, const f4& y) {
         if constexpr (DT == DT_F32) {
             *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
+        } else if constexpr (DT == DT_FP8) {
+            const float q = a.out_q;
+            *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
+                e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
         } else {
             bf16x4 h;
 #pragma unroll
@@ -230,26 +327,27 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     // feeds the matrix cores (deeper for small tiles, which have less MFMA
     // work per chunk to hide the load latency behind).
     constexpr int P = (MT * NT <= 2) ? 4 : 2;
-    const int K = ntaps * KC;
+    const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
+    auto load = [&](int kk, Frag (&A)[MT], Frag (&B)[NT]) {
+        if constexpr (DT == DT_FP8) {
+            loadA8(kk, A);
+            loadB8(kk, B);
+        } else {
+            loadA(kk / KC, kk % KC, A);
+            loadB(kk / KC, kk % KC, B);
+        }
+    };
     Frag Ab[P][MT], Bb[P][NT];
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
-        if (j < nk) {
-            const int kk = kslot + j * KSPLIT;
-            loadA(kk / KC, kk % KC, Ab[j]);
-            loadB(kk / KC, kk % KC, Bb[j]);
-        }
+        if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
     for (int k0 = 0; k0 < nk; k0 += P) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             const int k = k0 + j;
             if (k >= nk) break;
-            if (k + P - 1 < nk) {
-                const int kk = kslot + (k + P - 1) * KSPLIT;
-                loadA(kk / KC, kk % KC, Ab[(j + P - 1) % P]);
-                loadB(kk / KC, kk % KC, Bb[(j + P - 1) % P]);
-            }
+            if (k + P - 1 < nk) load(kslot + (k + P - 1) * KSPLIT, Ab[(j + P - 1) % P], Bb[(j + P - 1) % P]);
             compute(Ab[j], Bb[j]);
         }
     }
@@ -269,6 +367,17 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] += red[(((w - 1) * MT + mt) * NT + nt) * 64 + lane];
+    }
+
+    if constexpr (DT == DT_FP8) {
+        // undo the operand scales, then add the bias
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const f4 rs = *reinterpret_cast<const f4*>(a.rscale + co0 + mt * 16 + kg * 4);
+            const f4 b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = acc[mt][nt] * rs + b;
+        }
     }
 
     // ------------------------------------------------------------ epilogue
@@ -442,6 +551,13 @@ struct KernelEntry {
 #define LIC_K2B(TAG, CIN, LD, EP)                                                                \
     LIC_KSD(TAG, CIN, 4, 2, 4, 1, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 4, 2, 4, 4, LD, EP, DT_BF16), \
         LIC_KSD(TAG, CIN, 4, 2, 8, 8, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 1, 1, 8, 8, LD, EP, DT_BF16)
+// e4m3 operand variants (precision form): g_a and g_s
+#define LIC_KF(TAG, CIN, MT, NT, WV, LD, EP) LIC_KSD(TAG, CIN, MT, NT, WV, 1, LD, EP, DT_FP8)
+#define LIC_KGF(TAG, CIN, MT, NT, LD, EP) \
+    LIC_KSD(TAG, CIN, MT, NT, 4, 1, LD, EP, DT_FP8), LIC_KSD(TAG, CIN, MT, NT, 4, 4, LD, EP, DT_FP8)
+#define LIC_K2F(TAG, CIN, LD, EP)                                                              \
+    LIC_KSD(TAG, CIN, 4, 2, 4, 1, LD, EP, DT_FP8), LIC_KSD(TAG, CIN, 4, 2, 4, 4, LD, EP, DT_FP8), \
+        LIC_KSD(TAG, CIN, 4, 2, 8, 8, LD, EP, DT_FP8), LIC_KSD(TAG, CIN, 1, 1, 8, 8, LD, EP, DT_FP8)
 // the tile configurations of a non-GDN layer: large (4 m-tiles x 2 n-tiles,
 // 4 pixel-parallel waves), large with 4-way split-K, and small (1 x 1) with
 // 8-way split-K, for grids too small to fill the chip
@@ -481,6 +597,15 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    // e4m3 operands (precision form): g_a and g_s
+    LIC_KF(LIC_GA0, 128, 8, 2, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),
+    LIC_KGF(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KGF(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
+    LIC_KGF(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KGF(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KF(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KF(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
     // distilled synthesis network (64 hidden channels): forward in FP32 or
     // bf16 operands, input gradients (ReLU-masked) in FP32
     LIC_K2(TAG_DT1, 192, LD_I8, EP_RELU), LIC_K2(TAG_DT1, 320, LD_I8, EP_RELU),

@@ -4,6 +4,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 
 #include "codec.h"
 #include "packing.h"
@@ -102,6 +103,33 @@ uint16_t bf16_rne(float f)
     if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40u);
     u += 0x7fffu + ((u >> 16) & 1u);
     return (uint16_t)(u >> 16);
+}
+
+// OCP e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; largest
+// finite 448, subnormal step 2^-9, no infinities) of f, rounding to nearest
+// even and saturating at +-448.
+uint8_t e4m3_rne(float f)
+{
+    const uint8_t sign = std::signbit(f) ? 0x80 : 0x00;
+    double a = std::fabs((double)f);
+    if (!(a == a)) return 0x7f;                     // NaN
+    if (a >= 448.0) return sign | 0x7e;
+    // quantum of the binade (2^-9 below the smallest normal 2^-6)
+    int ex = 0;
+    (void)std::frexp(a, &ex);                       // a = m 2^ex, m in [0.5, 1)
+    int e = a > 0.0 ? ex - 1 : -6;
+    if (e < -6) e = -6;
+    const double q = std::ldexp(1.0, e - 3);
+    double m = a / q;                               // exact: q is a power of two
+    double r = std::nearbyint(m);                   // ties to even (default rounding mode)
+    double v = r * q;
+    if (v >= 448.0) return sign | 0x7e;
+    if (v == 0.0) return sign;
+    (void)std::frexp(v, &ex);
+    const int ve = ex - 1;
+    if (ve < -6) return sign | (uint8_t)std::lround(v / std::ldexp(1.0, -9));     // subnormal
+    const int mant = (int)std::lround(v / std::ldexp(1.0, ve - 3)) - 8;
+    return sign | (uint8_t)((ve + 7) << 3) | (uint8_t)mant;
 }
 
 bool build_tables(const ParamMap& P, int kind, int N, int M, std::vector<float>* medians,
@@ -251,8 +279,9 @@ int Codec::build_layers(const ParamMap& P)
         // bf16 operands for the analysis / synthesis transforms in the BF16
         // form; h_a and h_s always run in FP32 (fixed-order scale index)
         const bool is_gags = sp.id <= LIC_GA3 || sp.id >= LIC_GS0;
-        L.dt = (cfg.precision == LIC_PREC_BF16 && is_gags) ? DT_BF16 : DT_F32;
-        const int krgb = L.dt == DT_BF16 ? 96 : 80;   // 75 (tap, channel) pairs in whole K chunks
+        L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
+        // 75 (tap, channel) pairs in whole K chunks
+        const int krgb = L.dt == DT_BF16 ? 96 : L.dt == DT_FP8 ? 128 : 80;
         L.cin = sp.ld == LD_RGB ? krgb : ci;
         L.cop = L.rows ? 16 : co;
         if (sp.ld == LD_RGB && ci != 3) { err = "ga0 must take 3 channels"; return LIC_E_MODEL; }
@@ -269,7 +298,7 @@ int Codec::build_layers(const ParamMap& P)
         L.nphase = (int)ph.size();
 
         const size_t total = pm.idx.size();
-        const size_t esz = L.dt == DT_BF16 ? 2 : 4;
+        const size_t esz = L.dt == DT_BF16 ? 2 : L.dt == DT_FP8 ? 1 : 4;
         L.d_w = (uint8_t*)dev_alloc(total * esz);
         L.d_ph = (PhaseDesc*)dev_alloc(ph.size() * sizeof(PhaseDesc));
         L.d_bias = (float*)dev_alloc(L.cop * sizeof(float));
@@ -280,6 +309,34 @@ int Codec::build_layers(const ParamMap& P)
             std::vector<uint16_t> hb(total);
             for (size_t j = 0; j < total; ++j) hb[j] = bf16_rne(wp[j]);
             HIP_TRY(hipMemcpy(L.d_w, hb.data(), total * esz, hipMemcpyHostToDevice));
+        } else if (L.dt == DT_FP8) {
+            // per packed row: scale = max |w| / 448 over every tap and phase
+            // of the row, w8 = e4m3(w / scale); the epilogue multiplies by
+            // scale and by the input's own scale (1 / kActQ for e4m3
+            // activations, 1 for the image and for y_hat)
+            const size_t cin = (size_t)L.cin;
+            std::vector<double> amax(L.cop, 0.0);
+            for (size_t i = 0; i < ph.size(); ++i) {
+                const size_t end = i + 1 < ph.size() ? pm.off[i + 1] : total;
+                for (size_t j = pm.off[i]; j < end; ++j) {
+                    const size_t row = ((j - pm.off[i]) / cin) % (size_t)L.cop;
+                    amax[row] = std::max(amax[row], (double)std::fabs(wp[j]));
+                }
+            }
+            std::vector<float> wsc(L.cop);
+            for (int r = 0; r < L.cop; ++r) wsc[r] = amax[r] > 0.0 ? (float)(amax[r] / 448.0) : 1.0f;
+            std::vector<uint8_t> h8(total);
+            for (size_t i = 0; i < ph.size(); ++i) {
+                const size_t end = i + 1 < ph.size() ? pm.off[i + 1] : total;
+                for (size_t j = pm.off[i]; j < end; ++j) h8[j] = e4m3_rne(wp[j] / wsc[((j - pm.off[i]) / cin) % (size_t)L.cop]);
+            }
+            const float in_scale = (sp.ld == LD_F32) ? 1.0f / kActQ : 1.0f;
+            std::vector<float> rs(L.cop);
+            for (int r = 0; r < L.cop; ++r) rs[r] = wsc[r] * in_scale;
+            L.d_rscale = (float*)dev_alloc(L.cop * sizeof(float));
+            if (!L.d_rscale) { err = "device allocation failed"; return LIC_E_NOMEM; }
+            HIP_TRY(hipMemcpy(L.d_rscale, rs.data(), L.cop * sizeof(float), hipMemcpyHostToDevice));
+            HIP_TRY(hipMemcpy(L.d_w, h8.data(), total, hipMemcpyHostToDevice));
         } else {
             HIP_TRY(hipMemcpy(L.d_w, wp.data(), total * esz, hipMemcpyHostToDevice));
         }
@@ -372,6 +429,8 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.Wc = d.W;
     a.kk = L.k;
     a.pad = L.k / 2;
+    a.rscale = L.d_rscale;
+    a.out_q = kActQ;
 
     const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase};
     return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp);

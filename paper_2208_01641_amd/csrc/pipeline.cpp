@@ -22,7 +22,10 @@
 #include <algorithm>
 #include <chrono>
 
+#include <math.h>
+
 #include "codec.h"
+#include "distill_kernels.h"
 
 namespace lic {
 
@@ -266,6 +269,12 @@ void Codec::gpu_loop(int gi)
         }
         (void)hipEventRecord(ev_start[cur_ev], G.stream);
         G.cur = cur_ev;
+        t->judge = false;
+        if (G.kind == ST_GPU_GS && cfg.gs_mode == 2 && distill && !gs_fallback.load()) {
+            // judge the task holding frame f with f % judge_every == 0
+            const long f0 = gs_frames.fetch_add(t->nb);
+            t->judge = f0 % judge_every == 0 || f0 % judge_every + t->nb > judge_every;
+        }
         int (Codec::*body)(Task*, GpuStage&) =
             G.kind == ST_GPU_ENC ? &Codec::gpu_encode : G.kind == ST_GPU_HS ? &Codec::gpu_hs : &Codec::gpu_gs;
         if (!t->call && cfg.use_graphs) {
@@ -282,7 +291,8 @@ void Codec::gpu_loop(int gi)
                          hipSuccess;
             t->staged = true;
             if (!ok) t->fail(LIC_E_HIP, "input copy failed");
-            else if (gpu_stage_graph(t, G, body) == LIC_OK && G.kind == ST_GPU_GS)
+            // a judged task runs eagerly: the judge waits for its result
+            else if ((t->judge ? (this->*body)(t, G) : gpu_stage_graph(t, G, body)) == LIC_OK && G.kind == ST_GPU_GS)
                 for (int b = 0; b < t->nb && ok; ++b)
                     ok = hipMemcpyAsync(t->xhats[b], slots[t->slot].d_xhat + b * fsz, fsz * sizeof(float), kout,
                                         G.stream) == hipSuccess;
@@ -383,14 +393,115 @@ int Codec::gpu_gs(Task* t, GpuStage& G)
     const bool direct = !t->staged && dev && t->call && frames_contiguous(t, fsz, true);
     HIP_OK(hipMemcpyAsync(s.d_sym_y, s.h_sym_y, ny, hipMemcpyHostToDevice, st));
     float* xo = direct ? t->xhats[0] : s.d_xhat;
-    LAUNCH(LIC_GS0, s.d_sym_y, sc.a, nullptr, st);
-    LAUNCH(LIC_GS1, sc.a, sc.b, nullptr, st);
-    LAUNCH(LIC_GS2, sc.b, sc.a, nullptr, st);
-    LAUNCH(LIC_GS3, sc.a, xo, nullptr, st);
+    if (cfg.gs_mode != 0 && !distill) {
+        t->fail(LIC_E_STATE, "no distilled synthesis transform loaded");
+        return LIC_E_STATE;
+    }
+    if (cfg.gs_mode != 0 && !gs_fallback.load()) {
+        // the distilled net reads the same symbols and writes the same
+        // clamped, cropped image as the full g_s
+        std::string e;
+        const int r = distill->forward(s.d_sym_y, layers[LIC_GS0].d_mu_in, t->nb, d.Hy, d.Wy, nullptr, xo, d.H, d.W, st);
+        if (r != LIC_OK) {
+            t->fail(r, distill->err);
+            return r;
+        }
+        if (t->judge) {
+            const int rj = gs_judge(t, G, xo);
+            if (rj != LIC_OK) return rj;
+        }
+    } else {
+        LAUNCH(LIC_GS0, s.d_sym_y, sc.a, nullptr, st);
+        LAUNCH(LIC_GS1, sc.a, sc.b, nullptr, st);
+        LAUNCH(LIC_GS2, sc.b, sc.a, nullptr, st);
+        LAUNCH(LIC_GS3, sc.a, xo, nullptr, st);
+    }
     if (!direct && !t->staged)
         for (int b = 0; b < t->nb; ++b)
             HIP_OK(hipMemcpyAsync(t->xhats[b], s.d_xhat + b * fsz, fsz * sizeof(float),
                                   dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost, st));
+    return LIC_OK;
+}
+
+// Sampled check of the distilled g_s: frame 0 of the task also goes through
+// the full g_s; when the two reconstructions are further apart than the
+// threshold (PSNR of one against the other), the codec falls back to the
+// full g_s for good and this task's frames are decoded again with it.
+int Codec::gs_judge(Task* t, GpuStage& G, float* xo)
+{
+    const FrameDims& d = t->route->dims;
+    Slot& s = slots[t->slot];
+    StageScratch& sc = G.scratch;
+    hipStream_t st = G.stream;
+    const long fsz = 3L * d.H * d.W;
+    std::string e;
+    int r = LIC_OK;
+    if ((r = launch_layer(LIC_GS0, 1, d, s.d_sym_y, sc.a, nullptr, st, &e)) != LIC_OK ||
+        (r = launch_layer(LIC_GS1, 1, d, sc.a, sc.b, nullptr, st, &e)) != LIC_OK ||
+        (r = launch_layer(LIC_GS2, 1, d, sc.b, sc.a, nullptr, st, &e)) != LIC_OK ||
+        (r = launch_layer(LIC_GS3, 1, d, sc.a, d_judge_img, nullptr, st, &e)) != LIC_OK) {
+        t->fail(r, e);
+        return r;
+    }
+    const int chunk = 65536;
+    if (launch_sqdiff(xo, d_judge_img, fsz, chunk, d_judge_part, d_judge_part + (fsz + chunk - 1) / chunk, st) !=
+            hipSuccess ||
+        hipMemcpyAsync(h_judge, d_judge_part + (fsz + chunk - 1) / chunk, sizeof(float), hipMemcpyDeviceToHost, st) !=
+            hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess) {
+        t->fail(LIC_E_HIP, "judge failed");
+        return LIC_E_HIP;
+    }
+    const double mse = (double)h_judge[0] / (double)fsz;
+    const double db = mse > 0.0 ? 10.0 * log10(1.0 / mse) : 99.0;
+    gs_judge_last_db = db;
+    gs_judged++;
+    if (db < judge_db) {
+        gs_fallback.store(true);
+        if ((r = launch_layer(LIC_GS0, t->nb, d, s.d_sym_y, sc.a, nullptr, st, &e)) != LIC_OK ||
+            (r = launch_layer(LIC_GS1, t->nb, d, sc.a, sc.b, nullptr, st, &e)) != LIC_OK ||
+            (r = launch_layer(LIC_GS2, t->nb, d, sc.b, sc.a, nullptr, st, &e)) != LIC_OK ||
+            (r = launch_layer(LIC_GS3, t->nb, d, sc.a, xo, nullptr, st, &e)) != LIC_OK) {
+            t->fail(r, e);
+            return r;
+        }
+    }
+    return LIC_OK;
+}
+
+int Codec::load_distilled(const float* params, size_t n, float judge_psnr_db, int every)
+{
+    if (kind != 1 && kind != 0) { err = "no model"; return LIC_E_STATE; }
+    if (every < 1) { err = "judge interval must be positive"; return LIC_E_ARG; }
+    lic_distill_config dc;
+    lic_distill_default_config(&dc);
+    dc.M = M;
+    dc.F = 64;
+    dc.precision = cfg.precision == LIC_PREC_FP32 ? LIC_PREC_FP32 : LIC_PREC_BF16;   // e4m3 codecs: bf16 net
+    dc.max_batch = cfg.max_batch;
+    dc.max_hy = FrameDims(cfg.max_h, cfg.max_w).Hy;
+    dc.max_wy = FrameDims(cfg.max_h, cfg.max_w).Wy;
+    dc.train = 0;
+    dc.hip_device = cfg.hip_device;
+    std::unique_ptr<DistillNet> net(new DistillNet());
+    const int rc = net->create(dc, params, n);
+    if (rc != LIC_OK) {
+        err = net->err;
+        return rc;
+    }
+    if (!d_judge_img) {
+        const long fsz = 3L * cfg.max_h * cfg.max_w;
+        d_judge_img = (float*)dev_alloc(fsz * sizeof(float));
+        d_judge_part = (float*)dev_alloc(((fsz + 65535) / 65536 + 1) * sizeof(float));
+        h_judge = (float*)host_alloc(sizeof(float));
+        if (!d_judge_img || !d_judge_part || !h_judge) { err = "allocation failed"; return LIC_E_NOMEM; }
+    }
+    distill = std::move(net);
+    judge_db = judge_psnr_db;
+    judge_every = every;
+    gs_fallback.store(false);
+    gs_frames.store(0);
+    gs_judged.store(0);
     return LIC_OK;
 }
 
