@@ -255,7 +255,7 @@ typedef struct {
     int32_t  max_batch;        /* largest n of any call                              */
     int32_t  max_hy, max_wy;   /* largest latent grid (image = 16 hy x 16 wy)        */
     int32_t  train;            /* 1: allocate gradient and optimizer state           */
-    float    lr, beta1, beta2, eps, weight_decay;   /* AdamW                         */
+    double   lr, beta1, beta2, eps, weight_decay;   /* AdamW (update runs in FP32)   */
     int32_t  hip_device;
 } lic_distill_config;
 

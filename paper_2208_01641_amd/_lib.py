@@ -51,11 +51,11 @@ class DistillConfig(ctypes.Structure):
         ("max_hy", ctypes.c_int32),
         ("max_wy", ctypes.c_int32),
         ("train", ctypes.c_int32),
-        ("lr", ctypes.c_float),
-        ("beta1", ctypes.c_float),
-        ("beta2", ctypes.c_float),
-        ("eps", ctypes.c_float),
-        ("weight_decay", ctypes.c_float),
+        ("lr", ctypes.c_double),
+        ("beta1", ctypes.c_double),
+        ("beta2", ctypes.c_double),
+        ("eps", ctypes.c_double),
+        ("weight_decay", ctypes.c_double),
         ("hip_device", ctypes.c_int32),
     ]
 

@@ -309,10 +309,17 @@ int DistillNet::backward(const int8_t* sym, const float* mu, const float* target
 int DistillNet::update()
 {
     ++t;
-    const double c1 = 1.0 - pow((double)cfg.beta1, (double)t);
-    const double c2 = 1.0 - pow((double)cfg.beta2, (double)t);
-    D_TRY(launch_adamw(d_master, d_m, d_v, d_grad, nparam, cfg.lr, cfg.beta1, cfg.beta2, cfg.eps, cfg.weight_decay,
-                       (float)c1, (float)c2, stream));
+    AdamCoef k;
+    k.lr = (float)cfg.lr;
+    k.b1 = (float)cfg.beta1;
+    k.omb1 = (float)(1.0 - cfg.beta1);
+    k.b2 = (float)cfg.beta2;
+    k.omb2 = (float)(1.0 - cfg.beta2);
+    k.eps = (float)cfg.eps;
+    k.decay = (float)(1.0 - cfg.lr * cfg.weight_decay);
+    k.c1 = (float)(1.0 - pow(cfg.beta1, (double)t));
+    k.c2 = (float)(1.0 - pow(cfg.beta2, (double)t));
+    D_TRY(launch_adamw(d_master, d_m, d_v, d_grad, nparam, k, stream));
     return repack();
 }
 
@@ -337,11 +344,11 @@ void lic_distill_default_config(lic_distill_config* c)
     c->max_hy = 16;
     c->max_wy = 16;
     c->train = 1;
-    c->lr = 1e-3f;
-    c->beta1 = 0.9f;
-    c->beta2 = 0.999f;
-    c->eps = 1e-8f;
-    c->weight_decay = 0.01f;
+    c->lr = 1e-3;
+    c->beta1 = 0.9;
+    c->beta2 = 0.999;
+    c->eps = 1e-8;
+    c->weight_decay = 0.01;
     c->hip_device = 0;
 }
 

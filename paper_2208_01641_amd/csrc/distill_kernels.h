@@ -36,8 +36,12 @@ hipError_t launch_colsum(const float* g, long P, int co, int chunk, float* part,
 // dbias3[o] = sum of g over channel o
 hipError_t launch_mse(const float* pred, const float* target, int n, long plane, int chunks, float* g, float* part_sq,
                       float* part_g, float* loss, float* dbias3, hipStream_t s);
-hipError_t launch_adamw(float* w, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
-                        float wd, float c1, float c2, hipStream_t s);
+// AdamW step t: m = b1 m + (1 - b1) g, v = b2 v + (1 - b2) g^2,
+// w = w (1 - lr wd) - lr (m / c1) / (sqrt(v / c2) + eps), c = 1 - b^t
+struct AdamCoef {
+    float lr, b1, omb1, b2, omb2, eps, decay, c1, c2;
+};
+hipError_t launch_adamw(float* w, float* m, float* v, const float* g, long n, const AdamCoef& k, hipStream_t s);
 hipError_t launch_gather_pack(const float* master, const int32_t* idx, long n, float* out32, void* out16,
                               hipStream_t s);
 // *out = sum of (a - b)^2 over n elements

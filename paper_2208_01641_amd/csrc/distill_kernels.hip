@@ -239,17 +239,18 @@ __global__ void sum_planes3(const float* __restrict__ part, int n, int chunks, f
 
 // ------------------------------------------------------------------ AdamW
 // Decoupled weight decay, bias-corrected moments (c1 = 1 - b1^t, c2 = 1 - b2^t).
+// Coefficients come from the host, computed in double and rounded once.
 __global__ void adamw(float* __restrict__ w, float* __restrict__ m, float* __restrict__ v, const float* __restrict__ g,
-                      long n, float lr, float b1, float b2, float eps, float wd, float c1, float c2)
+                      long n, AdamCoef k)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    const float mi = k.b1 * m[i] + k.omb1 * gi;
+    const float vi = k.b2 * v[i] + k.omb2 * gi * gi;
     m[i] = mi;
     v[i] = vi;
-    w[i] = w[i] * (1.0f - lr * wd) - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    w[i] = w[i] * k.decay - k.lr * (mi / k.c1) / (sqrtf(vi / k.c2) + k.eps);
 }
 
 // packed[i] = master[idx[i]] (0 where idx < 0), as FP32 and optionally bf16
@@ -339,11 +340,9 @@ hipError_t launch_mse(const float* pred, const float* target, int n, long plane,
     return hipGetLastError();
 }
 
-hipError_t launch_adamw(float* w, float* m, float* v, const float* g, long n, float lr, float b1, float b2, float eps,
-                        float wd, float c1, float c2, hipStream_t s)
+hipError_t launch_adamw(float* w, float* m, float* v, const float* g, long n, const AdamCoef& k, hipStream_t s)
 {
-    hipLaunchKernelGGL(adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, lr, b1, b2, eps, wd,
-                       c1, c2);
+    hipLaunchKernelGGL(adamw, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, w, m, v, g, n, k);
     return hipGetLastError();
 }
 
