@@ -40,7 +40,8 @@ struct PhaseDesc {
     int32_t ntaps;
     int32_t oy, ox;          // output position = s_out * grid + (oy, ox)
     int32_t pad_;
-    const void* w;           // packed weights [ntaps][CoP][CIN] (device, float or bf16)
+    int64_t woff;            // element offset of this phase's packed weights
+                             // [ntaps][CoP][CIN] from ConvArgs::w
     int8_t dy[32], dx[32];   // tap offsets: input = s_in * grid + (dy, dx)
 };
 
@@ -49,6 +50,8 @@ struct ConvArgs {
     void* out;
     void* aux;
     const PhaseDesc* ph;     // [nphase] (device)
+    const void* w;           // packed weights of every phase (float, bf16 or e4m3)
+    const void* zero;        // >= 64 zero bytes: the source of out-of-image reads
     const float* bias;       // [CoP]
     const float* mu_in;      // LD_I8 offsets [CIN]
     const float* gamma;      // GDN [Co][Co]

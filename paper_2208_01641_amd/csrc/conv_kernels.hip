@@ -120,7 +120,11 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     const int tile = logical / a.nphase;
     const PhaseDesc* __restrict__ ph = a.ph + phase;
     const int ntaps = ph->ntaps;
-    const Elem* __restrict__ wbase = static_cast<const Elem*>(ph->w);
+    // tap table held across the wave: lane t keeps (dy, dx) of tap t, read
+    // back with readlane / bpermute (no memory access inside the K loop, so
+    // the wait for a chunk's operands never covers the prefetched ones)
+    const int tapv = lane < ntaps ? (((int)ph->dy[lane] & 0xffff) | ((int)ph->dx[lane] << 16)) : 0;
+    const Elem* __restrict__ wbase = static_cast<const Elem*>(a.w) + ph->woff;
     const int CoP = a.ncog * MT * 16;
     const int co0 = cog * MT * 16;
 
@@ -183,36 +187,35 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 B[nt] = v;
             }
         } else {
-            const int dy = ph->dy[t], dx = ph->dx[t];
+            const int tv = __builtin_amdgcn_readlane(tapv, t);
+            const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
                 const bool ok = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                // branch-free: out-of-image lanes read the zero page, so every
+                // lane issues its load and nothing waits on it before use
                 const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kc * KCH + kg * KE;
-                Frag v = {};
+                Frag v;
                 if constexpr (LD == LD_I8) {
                     // y_hat / z_hat = symbol + per-channel offset; zero outside the image
-                    if (ok) {
-                        const int8_t* src = static_cast<const int8_t*>(a.in) + off;
-                        const float* mu = a.mu_in + kc * KCH + kg * KE;
-                        if constexpr (KE == 4) {
-                            const uint32_t u = *reinterpret_cast<const uint32_t*>(src);
+                    const int8_t* src = ok ? static_cast<const int8_t*>(a.in) + off : static_cast<const int8_t*>(a.zero);
+                    const float* mu = ok ? a.mu_in + kc * KCH + kg * KE : static_cast<const float*>(a.zero);
+                    if constexpr (KE == 4) {
+                        const uint32_t u = *reinterpret_cast<const uint32_t*>(src);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) v[e] = (Elem)((float)(int8_t)(u >> (8 * e)) + mu[e]);
-                        } else {
-                            const uint2 u = *reinterpret_cast<const uint2*>(src);
+                        for (int e = 0; e < 4; ++e) v[e] = (Elem)((float)(int8_t)(u >> (8 * e)) + mu[e]);
+                    } else {
+                        const uint2 u = *reinterpret_cast<const uint2*>(src);
 #pragma unroll
-                            for (int e = 0; e < 4; ++e) {
-                                v[e] = (Elem)((float)(int8_t)(u.x >> (8 * e)) + mu[e]);
-                                v[4 + e] = (Elem)((float)(int8_t)(u.y >> (8 * e)) + mu[4 + e]);
-                            }
+                        for (int e = 0; e < 4; ++e) {
+                            v[e] = (Elem)((float)(int8_t)(u.x >> (8 * e)) + mu[e]);
+                            v[4 + e] = (Elem)((float)(int8_t)(u.y >> (8 * e)) + mu[4 + e]);
                         }
                     }
                 } else {
-                    if (ok) v = *reinterpret_cast<const Frag*>(static_cast<const Elem*>(a.in) + off);
-                    if constexpr (LD == LD_F32_ABS) {
-                        v[0] = fabsf(v[0]); v[1] = fabsf(v[1]); v[2] = fabsf(v[2]); v[3] = fabsf(v[3]);
-                    }
+                    const Elem* src = ok ? static_cast<const Elem*>(a.in) + off : static_cast<const Elem*>(a.zero);
+                    v = *reinterpret_cast<const Frag*>(src);
                 }
                 B[nt] = v;
             }
@@ -221,12 +224,14 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     auto compute = [&](const Frag (&A)[MT], const Frag (&B)[NT]) {
         if constexpr (DT == DT_F32) {
+            // |y| loader (h_a input): the magnitude is taken here, at use
+            auto bv = [&](int nt, int e) { return LD == LD_F32_ABS ? fabsf(B[nt][e]) : B[nt][e]; };
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], B[nt][e], acc[mt][nt]);
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], bv(nt, e), acc[mt][nt]);
         } else if constexpr (DT == DT_BF16) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -250,9 +255,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         const int t = f / CIN, c = f - (f / CIN) * CIN;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            Frag v = {};
-            if (t < ntaps) v = *reinterpret_cast<const Frag*>(wbase + ((long)t * CoP + co0 + mt * 16 + l16) * CIN + c);
-            A[mt] = v;
+            // past the last tap: read the zero page (no divergent load)
+            const Elem* src = t < ntaps ? wbase + ((long)t * CoP + co0 + mt * 16 + l16) * CIN + c
+                                        : static_cast<const Elem*>(a.zero);
+            A[mt] = *reinterpret_cast<const Frag*>(src);
         }
     };
     auto pack4 = [](float v0, float v1, float v2, float v3) -> int {
@@ -280,15 +286,17 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 }
 #pragma unroll
                 for (int q = 0; q < 8; ++q) v[q] = pack4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
-            } else if (t < ntaps) {
-                const int iy = gy[nt] * a.s_in + ph->dy[t], ix = gx[nt] * a.s_in + ph->dx[t];
-                const bool ok = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+            } else {
+                const int tv = __builtin_amdgcn_ds_bpermute(4 * (t < ntaps ? t : 0), tapv);
+                const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
+                const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
+                const bool ok = t < ntaps && pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
                 const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + c;
-                if (ok) {
+                {
                     if constexpr (LD == LD_I8) {
                         // y_hat = symbol + offset, rounded to e4m3 (exact for |y_hat| <= 16)
-                        const int8_t* src = static_cast<const int8_t*>(a.in) + off;
-                        const float* mu = a.mu_in + c;
+                        const int8_t* src = ok ? static_cast<const int8_t*>(a.in) + off : static_cast<const int8_t*>(a.zero);
+                        const float* mu = ok ? a.mu_in + c : static_cast<const float*>(a.zero);
                         const uint4 u0 = *reinterpret_cast<const uint4*>(src);
                         const uint4 u1 = *reinterpret_cast<const uint4*>(src + 16);
                         const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
@@ -298,7 +306,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                                          (float)(int8_t)(w[q] >> 16) + mu[4 * q + 2],
                                          (float)(int8_t)(w[q] >> 24) + mu[4 * q + 3]);
                     } else {
-                        v = *reinterpret_cast<const Frag*>(static_cast<const Elem*>(a.in) + off);
+                        const Elem* src = ok ? static_cast<const Elem*>(a.in) + off : static_cast<const Elem*>(a.zero);
+                        v = *reinterpret_cast<const Frag*>(src);
                     }
                 }
             }
@@ -342,7 +351,17 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
         if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
-    for (int k0 = 0; k0 < nk; k0 += P) {
+    // steady state: every step issues its prefetch unconditionally, so the
+    // wait before a chunk's MFMAs only covers that chunk's own loads
+    int k0 = 0;
+    for (; k0 + 2 * P - 2 < nk; k0 += P) {
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            load(kslot + (k0 + j + P - 1) * KSPLIT, Ab[(j + P - 1) % P], Bb[(j + P - 1) % P]);
+            compute(Ab[j], Bb[j]);
+        }
+    }
+    for (; k0 < nk; k0 += P) {
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             const int k = k0 + j;

@@ -66,7 +66,7 @@ int DistillNet::build_layer(Layer& L, int tag, int ld, int ep, int dt, PackKind 
     L.w_off = (long)idx.size();
     for (int32_t j : pm.idx) idx.push_back(j < 0 ? -1 : (int32_t)(src_w + j));
     L.ph = pm.ph;
-    for (size_t i = 0; i < L.ph.size(); ++i) L.ph[i].w = reinterpret_cast<const void*>((uintptr_t)(L.w_off + pm.off[i]));
+    for (size_t i = 0; i < L.ph.size(); ++i) L.ph[i].woff = (int64_t)(L.w_off + pm.off[i]);
     if (src_b >= 0) {
         L.b_off = (long)bidx.size();
         for (int32_t j : pm.bias_idx) bidx.push_back(j < 0 ? -1 : (int32_t)(src_b + j));
@@ -117,12 +117,7 @@ int DistillNet::create(const lic_distill_config& c, const float* params, size_t 
     D_TRY(hipMemcpy(d_pidx, idx.data(), n_arena * sizeof(int32_t), hipMemcpyHostToDevice));
     D_TRY(hipMemset(d_zero, 0, 1024 * sizeof(float)));
     for (Layer* L : {&fwd[0], &fwd[1], &fwd[2], &dg2, &dg3}) {
-        const bool b16 = L->shape.dt == DT_BF16;
-        std::vector<PhaseDesc> ph = L->ph;
-        for (auto& d : ph) {
-            const long e = (long)(uintptr_t)d.w;
-            d.w = b16 ? (const void*)((const uint16_t*)d_arena16 + e) : (const void*)(d_arena32 + e);
-        }
+        const std::vector<PhaseDesc>& ph = L->ph;
         L->d_ph = (PhaseDesc*)alloc(ph.size() * sizeof(PhaseDesc));
         if (!L->d_ph) { err = "device allocation failed"; return LIC_E_NOMEM; }
         D_TRY(hipMemcpy(L->d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
@@ -193,6 +188,8 @@ int DistillNet::forward(const int8_t* sym, const float* mu, int n, int hy, int w
         a.out = out;
         a.aux = aux;
         a.ph = L.d_ph;
+        a.w = L.shape.dt == DT_BF16 ? d_arena16 : (const void*)d_arena32;
+        a.zero = d_zero;
         a.bias = L.b_off >= 0 ? d_arena32 + L.b_off : d_zero;
         a.mu_in = mu ? mu : d_zero;
         a.n = n;
@@ -276,6 +273,8 @@ int DistillNet::backward(const int8_t* sym, const float* mu, const float* target
         a.out = out;
         a.aux = const_cast<void*>(mask);
         a.ph = L.d_ph;
+        a.w = d_arena32;
+        a.zero = d_zero;
         a.bias = d_zero;
         a.mu_in = d_zero;
         a.n = n;

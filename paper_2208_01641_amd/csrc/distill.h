@@ -22,7 +22,7 @@ struct DistillNet {
         int co = 0, k = 0, s = 0, p = 0;
         long w_off = 0;                  // element offset of the packed weights in the arenas
         long b_off = -1;                 // element offset of the packed bias in arena32 (-1: none)
-        std::vector<PhaseDesc> ph;       // .w holds the element offset until upload
+        std::vector<PhaseDesc> ph;       // .woff: element offset in the arena
         PhaseDesc* d_ph = nullptr;
     };
 

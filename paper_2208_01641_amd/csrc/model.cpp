@@ -340,7 +340,7 @@ int Codec::build_layers(const ParamMap& P)
         } else {
             HIP_TRY(hipMemcpy(L.d_w, wp.data(), total * esz, hipMemcpyHostToDevice));
         }
-        for (size_t i = 0; i < ph.size(); ++i) ph[i].w = L.d_w + pm.off[i] * esz;
+        for (size_t i = 0; i < ph.size(); ++i) ph[i].woff = (int64_t)pm.off[i];
         HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
         L.host_ph = ph;
         std::vector<float> bias(L.cop, 0.0f);
@@ -407,6 +407,8 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.out = out;
     a.aux = aux;
     a.ph = L.d_ph;
+    a.w = L.d_w;
+    a.zero = d_zero;
     a.bias = L.d_bias;
     a.mu_in = L.d_mu_in;
     a.gamma = L.d_gamma;
