@@ -333,9 +333,11 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     // K loop over this wave's chunks k = kslot, kslot + KSPLIT, ..., with a
     // register ring of P chunk buffers: P - 1 chunks are in flight while one
-    // feeds the matrix cores (deeper for small tiles, which have less MFMA
-    // work per chunk to hide the load latency behind).
-    constexpr int P = (MT * NT <= 2) ? 4 : 2;
+    // feeds the matrix cores (as deep as the register budget allows: small
+    // tiles have less MFMA work per chunk to hide the load latency behind).
+    constexpr int STAGE = (MT + NT) * (int)(sizeof(Frag) / 4);      // VGPRs per chunk buffer
+    constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
+    constexpr int P = BUDGET / STAGE < 2 ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
     auto load = [&](int kk, Frag (&A)[MT], Frag (&B)[NT]) {

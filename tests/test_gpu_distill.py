@@ -124,9 +124,12 @@ def test_adamw_step_matches_oracle_update(torch_dev):
             assert np.array_equal(g, g_ref)
         oracle.adamw_step(w, m, v, g.astype(np.float64), t, lr=1e-3, wd=0.01)
         assert d.step_count == t
+        # FP32 update against FP64: a few ulp per element, relative to each
+        # array's scale (the moments cancel where successive gradients differ
+        # in sign, so an element-relative bound would be meaningless there)
         np.testing.assert_allclose(d.get(0), w, rtol=0, atol=2e-6)
-        np.testing.assert_allclose(d.get(1), m, rtol=2e-6, atol=1e-12)
-        np.testing.assert_allclose(d.get(2), v, rtol=2e-6, atol=1e-18)
+        np.testing.assert_allclose(d.get(1), m, rtol=2e-6, atol=1e-6 * np.abs(m).max())
+        np.testing.assert_allclose(d.get(2), v, rtol=2e-6, atol=1e-6 * np.abs(v).max())
         assert float(loss.item()) > 0
     d.close()
 
