@@ -92,7 +92,7 @@ def cpu_baseline(x_np, P, blob, N, M):
 
 
 def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflight, slices, zero_copy,
-                 timed_layers, copy_probe_mib=0):
+                 timed_layers, copy_probe_mib=0, host_frames=False):
     """Creates a codec, pipelines warmup + steps frames through encode->decode
     and returns the measurements (and the first frame for the CPU baseline)."""
     import numpy as np
@@ -108,6 +108,9 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
                   max_batch=batch)
     frames = synth.frames_sinusoid_torch(H, W, range(steps + warmup), device="cuda")
     out = torch.empty_like(frames)
+    if host_frames:                        # frames and reconstructions in pinned host memory (PCIe both ways)
+        frames = frames.cpu().pin_memory()
+        out = out.cpu().pin_memory()
     if copy_probe_mib:
         src = torch.ones(copy_probe_mib << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -151,7 +154,7 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
     return res, x0, P, blob
 
 
-def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7):
+def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7, use_graphs=1):
     """16 concurrent streams (8 x 360p, 4 x 720p, 4 x 1080p), Poisson frame
     arrivals at 30 fps per stream, served through submit/poll with
     continuous batching (per-size buckets, batches of up to 4, captured HIP
@@ -168,7 +171,7 @@ def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7):
     P = synth.model_params(1, N, M)
     blob = synth.weight_blob(P, 1, N, M)
     codec = Codec(blob, kind=1, N=N, M=M, hs_out=1, precision=precision, y_slices=4, entropy_threads=threads,
-                  zero_copy=1, max_in_flight=8, max_h=1080, max_w=1920, max_batch=4, use_graphs=1)
+                  zero_copy=1, max_in_flight=8, max_h=1080, max_w=1920, max_batch=4, use_graphs=use_graphs)
     sids = [codec.open_stream(H, W) for H, W in sizes]
     frames = [synth.frames_sinusoid_torch(H, W, range(4), stream=s, device="cuda") for s, (H, W) in enumerate(sizes)]
     ring = 48
@@ -426,6 +429,15 @@ def main():
         r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=0, batch=1, steps=60, warmup=5,
                                   inflight=1, **common)
         var["fp32_720p_one_frame_in_flight"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        # ladder rungs: symbols and indices through device buffers and async
+        # copies instead of zero-copy stores; frames in pinned host memory
+        zc = dict(common, zero_copy=0)
+        r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=0, batch=1, steps=150, warmup=10,
+                                  inflight=args.inflight, **zc)
+        var["fp32_720p_async_copies"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms")})
+        r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=0, batch=1, steps=150, warmup=10,
+                                  inflight=args.inflight, host_frames=True, **common)
+        var["fp32_720p_host_frames"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms")})
         r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=1, batch=1, steps=300, warmup=30,
                                   inflight=args.inflight, **common)
         var["bf16_720p"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
@@ -447,6 +459,7 @@ def main():
         var["fp8_1080p_n192_m320_batch4"]["d_psnr_db_vs_fp32"] = round(big["fp8"]["psnr_db"] - big["fp32"]["psnr_db"], 4)
         var["fp8_1080p_n192_m320_batch4"]["d_bpp_vs_fp32"] = round(big["fp8"]["bpp"] - big["fp32"]["bpp"], 5)
         var["serving_16_streams_bf16"] = _round(run_serving(precision=1, threads=threads))
+        var["serving_16_streams_bf16_no_graphs"] = _round(run_serving(precision=1, threads=threads, use_graphs=0))
         if args.distill_pairs > 0:
             var["distilled_gs"] = run_distilled(pairs=args.distill_pairs, steps=args.distill_steps, threads=threads)
         res["variants"] = var

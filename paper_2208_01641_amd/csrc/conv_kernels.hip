@@ -274,18 +274,30 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 // flattened (tap, channel) pairs of the 3-channel NCHW input
                 const float* in = static_cast<const float*>(a.in);
                 const int kk = a.kk, kn = 3 * a.kk * a.kk;
-                float x[KE];
+                // walk (u, w, ch) incrementally from k = c: no division per element
+                int tap = c / 3, ch = c - 3 * (c / 3);
+                int u = tap / kk, w = tap - kk * (tap / kk);
+                const long plane = (long)a.Hin * a.Win;
+                const float* base = in + (long)img[nt] * 3 * plane;
 #pragma unroll
-                for (int e = 0; e < KE; ++e) {
-                    const int k = c + e;
-                    const int tap = k / 3, ch = k - 3 * (k / 3);
-                    const int u = tap / kk, w = tap - kk * (tap / kk);
-                    const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
-                    const bool ok = pv[nt] && t < ntaps && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-                    x[e] = ok ? in[(((long)img[nt] * 3 + ch) * a.Hin + iy) * a.Win + ix] : 0.0f;
+                for (int q = 0; q < 8; ++q) {
+                    float x4[4];
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int k = c + 4 * q + i;
+                        const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
+                        const bool ok = pv[nt] && t < ntaps && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                        x4[i] = ok ? base[ch * plane + (long)iy * a.Win + ix] : 0.0f;
+                        if (++ch == 3) {
+                            ch = 0;
+                            if (++w == kk) {
+                                w = 0;
+                                ++u;
+                            }
+                        }
+                    }
+                    v[q] = pack4(x4[0], x4[1], x4[2], x4[3]);
                 }
-#pragma unroll
-                for (int q = 0; q < 8; ++q) v[q] = pack4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]);
             } else {
                 const int tv = __builtin_amdgcn_ds_bpermute(4 * (t < ntaps ? t : 0), tapv);
                 const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
