@@ -395,6 +395,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         }
         __syncthreads();
         if (kslot > 0) return;
+        // one partner wave at a time (keeps the partial sums out of registers)
+#pragma unroll 1
         for (int w = 1; w < KSPLIT; ++w)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
