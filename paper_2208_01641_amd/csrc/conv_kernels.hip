@@ -23,6 +23,8 @@
 // GDN contraction over channels needs - no data movement between the two.
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "../../include/lic.h"
 #include "conv_args.h"
 #include "kernels.h"
@@ -101,6 +103,14 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     using Frag = typename Prec<DT>::Frag;
     using Elem = typename Prec<DT>::Elem;
     constexpr int KCH = Prec<DT>::KCH, KE = Prec<DT>::KE;
+    // int8 symbols stay raw in the prefetch ring (with their offsets) and are
+    // converted when the chunk is used, so the conversion never waits on a
+    // load that is still in flight
+    struct I8Raw {
+        uint32_t w[KE / 4];
+        float mu[KE];
+    };
+    using BRaw = typename std::conditional<LD == LD_I8 && DT != DT_FP8, I8Raw, Frag>::type;
     constexpr int KC = DT == DT_FP8 ? 1 : CIN / KCH;
     static_assert(DT == DT_FP8 ? CIN % 32 == 0 : CIN % KCH == 0, "whole K chunks");
     static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
@@ -164,7 +174,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
     };
 
-    auto loadB = [&](int t, int kc, Frag (&B)[NT]) {
+    auto loadB = [&](int t, int kc, BRaw (&B)[NT]) {
         if constexpr (LD == LD_RGB) {
             // kk x kk taps over 3 NCHW channels flattened, k = (kk u + v) * 3 + c,
             // zero beyond 3 kk^2 (g_a's first layer: kk = 5, stride 2, pad 2)
@@ -196,42 +206,58 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 // branch-free: out-of-image lanes read the zero page, so every
                 // lane issues its load and nothing waits on it before use
                 const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kc * KCH + kg * KE;
-                Frag v;
-                if constexpr (LD == LD_I8) {
+                if constexpr (LD == LD_I8 && DT != DT_FP8) {
                     // y_hat / z_hat = symbol + per-channel offset; zero outside the image
                     const int8_t* src = ok ? static_cast<const int8_t*>(a.in) + off : static_cast<const int8_t*>(a.zero);
                     const float* mu = ok ? a.mu_in + kc * KCH + kg * KE : static_cast<const float*>(a.zero);
+                    I8Raw r;
                     if constexpr (KE == 4) {
-                        const uint32_t u = *reinterpret_cast<const uint32_t*>(src);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) v[e] = (Elem)((float)(int8_t)(u >> (8 * e)) + mu[e]);
+                        r.w[0] = *reinterpret_cast<const uint32_t*>(src);
                     } else {
                         const uint2 u = *reinterpret_cast<const uint2*>(src);
-#pragma unroll
-                        for (int e = 0; e < 4; ++e) {
-                            v[e] = (Elem)((float)(int8_t)(u.x >> (8 * e)) + mu[e]);
-                            v[4 + e] = (Elem)((float)(int8_t)(u.y >> (8 * e)) + mu[4 + e]);
-                        }
+                        r.w[0] = u.x;
+                        r.w[1] = u.y;
                     }
+#pragma unroll
+                    for (int e = 0; e < KE; e += 4) *reinterpret_cast<f4*>(&r.mu[e]) = *reinterpret_cast<const f4*>(mu + e);
+                    B[nt] = r;
                 } else {
                     const Elem* src = ok ? static_cast<const Elem*>(a.in) + off : static_cast<const Elem*>(a.zero);
-                    v = *reinterpret_cast<const Frag*>(src);
+                    B[nt] = *reinterpret_cast<const Frag*>(src);
                 }
-                B[nt] = v;
             }
         }
     };
 
-    auto compute = [&](const Frag (&A)[MT], const Frag (&B)[NT]) {
+    // the B operand of a ring entry: int8 symbols + offsets converted, |y|
+    // taken for the h_a input, everything else as loaded
+    auto cook = [&](const BRaw& r) -> Frag {
+        if constexpr (LD == LD_I8 && DT != DT_FP8) {
+            Frag v;
+#pragma unroll
+            for (int e = 0; e < KE; ++e) v[e] = (Elem)((float)(int8_t)(r.w[e / 4] >> (8 * (e % 4))) + r.mu[e]);
+            return v;
+        } else if constexpr (LD == LD_F32_ABS) {
+            Frag v = r;
+#pragma unroll
+            for (int e = 0; e < KE; ++e) v[e] = fabsf(v[e]);
+            return v;
+        } else {
+            return r;
+        }
+    };
+
+    auto compute = [&](const Frag (&A)[MT], const BRaw (&Braw)[NT]) {
+        Frag B[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) B[nt] = cook(Braw[nt]);
         if constexpr (DT == DT_F32) {
-            // |y| loader (h_a input): the magnitude is taken here, at use
-            auto bv = [&](int nt, int e) { return LD == LD_F32_ABS ? fabsf(B[nt][e]) : B[nt][e]; };
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
                 for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], bv(nt, e), acc[mt][nt]);
+                    for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma16x16x4(A[mt][e], B[nt][e], acc[mt][nt]);
         } else if constexpr (DT == DT_BF16) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
@@ -347,12 +373,12 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     // register ring of P chunk buffers: P - 1 chunks are in flight while one
     // feeds the matrix cores (as deep as the register budget allows: small
     // tiles have less MFMA work per chunk to hide the load latency behind).
-    constexpr int STAGE = (MT + NT) * (int)(sizeof(Frag) / 4);      // VGPRs per chunk buffer
+    constexpr int STAGE = (MT * (int)sizeof(Frag) + NT * (int)sizeof(BRaw)) / 4;   // VGPRs per chunk buffer
     constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
     constexpr int P = BUDGET / STAGE < 2 ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
-    auto load = [&](int kk, Frag (&A)[MT], Frag (&B)[NT]) {
+    auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) {
         if constexpr (DT == DT_FP8) {
             loadA8(kk, A);
             loadB8(kk, B);
@@ -361,7 +387,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             loadB(kk / KC, kk % KC, B);
         }
     };
-    Frag Ab[P][MT], Bb[P][NT];
+    Frag Ab[P][MT];
+    BRaw Bb[P][NT];
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
         if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
