@@ -110,7 +110,13 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         uint32_t w[KE / 4];
         float mu[KE];
     };
-    using BRaw = typename std::conditional<LD == LD_I8 && DT != DT_FP8, I8Raw, Frag>::type;
+    // image values likewise stay FP32 in the ring in the bf16 form
+    struct RgbRaw {
+        float x[KE];
+    };
+    using BRaw = typename std::conditional<
+        LD == LD_I8 && DT != DT_FP8, I8Raw,
+        typename std::conditional<LD == LD_RGB && DT == DT_BF16, RgbRaw, Frag>::type>::type;
     constexpr int KC = DT == DT_FP8 ? 1 : CIN / KCH;
     static_assert(DT == DT_FP8 ? CIN % 32 == 0 : CIN % KCH == 0, "whole K chunks");
     static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
@@ -179,22 +185,42 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             // kk x kk taps over 3 NCHW channels flattened, k = (kk u + v) * 3 + c,
             // zero beyond 3 kk^2 (g_a's first layer: kk = 5, stride 2, pad 2)
             const float* in = static_cast<const float*>(a.in);
+            const float* zero = static_cast<const float*>(a.zero);
             const int kk = a.kk, kn = 3 * a.kk * a.kk;
+            const long plane = (long)a.Hin * a.Win;
+            const int k0 = kc * KCH + kg * KE;
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                Frag v;
+                // walk (u, w, ch) from k0 without a division per element;
+                // outside the image (or past 3 kk^2) read the zero page
+                int tap = k0 / 3, ch = k0 - 3 * (k0 / 3);
+                int u = tap / kk, w = tap - kk * (tap / kk);
+                const float* base = in + (long)img[nt] * 3 * plane;
+                float x[KE];
 #pragma unroll
                 for (int e = 0; e < KE; ++e) {
-                    const int k = kc * KCH + kg * KE + e;
-                    const int tap = k / 3, c = k - 3 * (k / 3);
-                    const int u = tap / kk, w = tap - kk * (tap / kk);
                     const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
-                    const bool ok = pv[nt] && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-                    float val = 0.0f;
-                    if (ok) val = in[(((long)img[nt] * 3 + c) * a.Hin + iy) * a.Win + ix];
-                    v[e] = (Elem)val;
+                    const bool ok = pv[nt] && k0 + e < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+                    x[e] = *(ok ? base + ch * plane + (long)iy * a.Win + ix : zero);
+                    if (++ch == 3) {
+                        ch = 0;
+                        if (++w == kk) {
+                            w = 0;
+                            ++u;
+                        }
+                    }
                 }
-                B[nt] = v;
+                if constexpr (DT == DT_BF16) {
+                    RgbRaw r;
+#pragma unroll
+                    for (int e = 0; e < KE; ++e) r.x[e] = x[e];
+                    B[nt] = r;
+                } else {
+                    Frag v;
+#pragma unroll
+                    for (int e = 0; e < KE; ++e) v[e] = (Elem)x[e];
+                    B[nt] = v;
+                }
             }
         } else {
             const int tv = __builtin_amdgcn_readlane(tapv, t);
@@ -236,6 +262,11 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             Frag v;
 #pragma unroll
             for (int e = 0; e < KE; ++e) v[e] = (Elem)((float)(int8_t)(r.w[e / 4] >> (8 * (e % 4))) + r.mu[e]);
+            return v;
+        } else if constexpr (LD == LD_RGB && DT == DT_BF16) {
+            Frag v;
+#pragma unroll
+            for (int e = 0; e < KE; ++e) v[e] = (Elem)r.x[e];
             return v;
         } else if constexpr (LD == LD_F32_ABS) {
             Frag v = r;
@@ -375,7 +406,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     // tiles have less MFMA work per chunk to hide the load latency behind).
     constexpr int STAGE = (MT * (int)sizeof(Frag) + NT * (int)sizeof(BRaw)) / 4;   // VGPRs per chunk buffer
     constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
-    constexpr int P = BUDGET / STAGE < 2 ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
+    // (the image loader has only a handful of chunks: keep its ring short)
+    constexpr int P = (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
     auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) {
