@@ -229,3 +229,44 @@ def test_sampled_judge_keeps_or_falls_back(torch_dev):
     assert torch.equal(o2, ref_full)
     for c in (full, kept, fb):
         c.close()
+
+
+def test_serving_decodes_with_the_distilled_gs_in_graphs(torch_dev):
+    """Serving path (captured graphs, batches of up to 2): each decoded frame
+    equals the distilled net's output for its symbols; judged tasks (every
+    2nd frame here) run eagerly and keep the distilled output."""
+    torch = torch_dev
+    from gpu_util import make_codec
+    from paper_2208_01641_amd import Distill
+    H, W = 128, 192
+    Pd = _params()
+    c, _ = make_codec(1, 128, M, max_h=H, max_w=W, y_slices=2, entropy_threads=4, max_in_flight=3, max_batch=2,
+                      use_graphs=1, gs_mode=2)
+    c.load_distilled(Pd, judge_psnr_db=-1e9, judge_every=2)
+    x = _frames(torch, H, W, 6, stream=8)
+    bits = c.encode(x)
+    sid = c.open_stream(H, W)
+    for rep in range(2):                         # second round replays the graphs
+        outs, tick, keep = {}, {}, []
+        for i, b in enumerate(bits):
+            outs[i] = torch.empty((3, H, W), device="cuda")
+            keep.append(np.frombuffer(b, np.uint8).copy())      # alive until polled
+            tick[c.submit_decode(sid, keep[-1], outs[i])] = i
+        got = []
+        import time
+        t0 = time.time()
+        while len(got) < len(tick):
+            got += c.poll(64, 20000)
+            assert time.time() - t0 < 60
+        assert all(r["status"] == 0 for r in got)
+        torch.cuda.synchronize()
+        ref = torch.empty_like(x)
+        d = Distill(Pd, M, F, max_batch=6, max_hy=H // 16, max_wy=W // 16, train=False)
+        d.forward(_symbols(torch, c, x), x_hat=ref)
+        d.close()
+        for i in range(len(bits)):
+            assert torch.equal(outs[i], ref[i]), (rep, i)
+    st = c.stats()
+    assert st["gs_judged"] >= 2 and st["gs_fallback"] == 0
+    c.close_stream(sid)
+    c.close()
