@@ -127,6 +127,7 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
     dt = time.perf_counter() - t0
     lat = codec.latencies_ms()
     st = codec.stats()
+    progress(f"{H}x{W} N={N} M={M} precision={precision} batch={batch} in_flight={inflight}: {steps / dt:.1f} frames/s")
     layers = {}
     for L in timed_layers:
         ms, n = codec.layer_time(L)
@@ -167,6 +168,7 @@ def run_serving(*, precision, threads, duration_s=4.0, warmup_s=1.0, seed=7, use
     from paper_2208_01641_amd import Codec
 
     N, M = 128, 192
+    progress(f"serving: 16 streams, precision={precision}, graphs={use_graphs}")
     sizes = [(360, 640)] * 8 + [(720, 1280)] * 4 + [(1080, 1920)] * 4
     P = synth.model_params(1, N, M)
     blob = synth.weight_blob(P, 1, N, M)
@@ -260,10 +262,12 @@ def run_distilled(*, pairs, steps, threads, batch=32, holdout=256, deploy_frames
     for i in range(total):                 # one generator stream per crop
         imgs[i] = synth.frames_sinusoid_torch(256, 256, [0], stream=10 ** 6 + i, device="cuda")[0]
     torch.cuda.synchronize()
+    progress(f"distilled g_s: {total} crops generated")
     t0 = time.perf_counter()
     sym, rec = dtr.build_pairs(teacher, imgs)
     torch.cuda.synchronize()
     t_pairs = time.perf_counter() - t0
+    progress(f"distilled g_s: {total} (y_hat, x_hat) pairs in {t_pairs:.1f} s")
     teacher.close()
     net = Distill(synth.distill_params(M, F), M, F, max_batch=batch, max_hy=16, max_wy=16)
     dtr.train(net, sym[:pairs], rec[:pairs], 5, batch, seed=seed + 1)          # warm-up (discarded state below)
@@ -272,7 +276,12 @@ def run_distilled(*, pairs, steps, threads, batch=32, holdout=256, deploy_frames
     net.set(2, np.zeros(net.n_params, np.float32))
     net.step_count = 0
     t0 = time.perf_counter()
-    losses = dtr.train(net, sym[:pairs], rec[:pairs], steps, batch, seed=seed)
+    losses = []
+    for s0 in range(0, steps, 1000):            # chunks of 1000 steps, with a progress line each
+        n = min(1000, steps - s0)
+        losses.append(dtr.train(net, sym[:pairs], rec[:pairs], n, batch, seed=seed + s0))
+        progress(f"distilled g_s: {s0 + n}/{steps} steps, loss {float(losses[-1][-50:].mean()):.5f}")
+    losses = np.concatenate(losses)
     t_train = time.perf_counter() - t0
     fid, gap = dtr.evaluate(net, sym[pairs:], rec[pairs:], imgs[pairs:])
     T = dtr.judge_threshold(fid, gap)
@@ -312,6 +321,7 @@ def run_distilled(*, pairs, steps, threads, batch=32, holdout=256, deploy_frames
         else:
             out["full_xr"] = xr
         out[name] = _round(r)
+        progress(f"distilled g_s: 720p decode {name}: {r['decode_fps']:.1f} frames/s")
         c.close()
     full = out.pop("full_xr")
     del full, frames
@@ -333,6 +343,12 @@ def run_distilled(*, pairs, steps, threads, batch=32, holdout=256, deploy_frames
 def synth_flat(P):
     from paper_2208_01641_amd.distill import flatten
     return flatten(P)
+
+
+def progress(msg):
+    """One line per finished piece of work, on stderr (the JSON line is the
+    only stdout output)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def _round(d, nd=3):
