@@ -193,9 +193,12 @@ void Codec::server_loop()
 void Codec::server_finish(Task* t)
 {
     Server& S = *server;
-    const Slot& sl = slots[t->slot];
-    std::vector<lic_result> res(t->nb);
-    for (int b = 0; b < t->nb; ++b) {
+    // the batcher reuses this task as soon as its slot is free again, so
+    // everything needed afterwards is read now and the slot is freed last
+    const int nb = t->nb, slot = t->slot;
+    const Slot& sl = slots[slot];
+    std::vector<lic_result> res(nb);
+    for (int b = 0; b < nb; ++b) {
         Request* r = t->req[b];
         lic_result& o = res[b];
         memset(&o, 0, sizeof(o));
@@ -214,15 +217,15 @@ void Codec::server_finish(Task* t)
         delete r;
         t->req[b] = nullptr;
     }
-    free_slots.push(t->slot);
     {
         std::lock_guard<std::mutex> g(S.done_m);
         for (auto& o : res) S.done.push_back(o);
     }
     {
         std::lock_guard<std::mutex> g(S.m);
-        S.pending -= t->nb;
+        S.pending -= nb;
     }
+    free_slots.push(slot);
     S.done_cv.notify_all();
 }
 

@@ -109,3 +109,37 @@ def test_admission_by_budget(torch_dev):
     with pytest.raises(LicError):
         c.open_stream(512, 256)                   # larger than max_h x max_w
     c.close()
+
+
+@pytest.mark.timeout(180)
+def test_slot_reuse_with_varying_batches_drains_and_closes(torch_dev):
+    """Many requests over three frame sizes through two pool slots, batches
+    of 1..4: every result arrives once, the pending count returns to zero and
+    close() returns (a finished task's slot is reused by the batcher only
+    after the task's bookkeeping is done)."""
+    torch = torch_dev
+    sizes = [(128, 128), (128, 192), (192, 256)]
+    c, _ = make_codec(1, 128, 192, max_h=192, max_w=256, y_slices=1, entropy_threads=4, max_in_flight=2,
+                      max_batch=4, use_graphs=1)
+    sids = [c.open_stream(H, W) for H, W in sizes]
+    frames = {s: torch.from_numpy(synth.frame_sinusoid(H, W, t=0, stream=20 + s)).cuda() for s, (H, W) in
+              enumerate(sizes)}
+    rng = np.random.default_rng(3)
+    order = rng.integers(0, 3, 120)
+    outs, tick = {}, {}
+    for i, s in enumerate(order):
+        outs[i] = np.zeros(c.max_stream_bytes(*sizes[s]), np.uint8)
+        tick[c.submit_encode(sids[s], frames[int(s)], outs[i])] = i
+    res = _drain(c, len(tick), timeout_s=120.0)
+    assert sorted(tick[r["ticket"]] for r in res) == list(range(len(order)))
+    assert all(r["status"] == 0 for r in res)
+    bits = {tick[r["ticket"]]: outs[tick[r["ticket"]]][:r["bytes"]].copy() for r in res}
+    imgs, dtick = {}, {}
+    for i, s in enumerate(order):
+        H, W = sizes[s]
+        imgs[i] = torch.empty((3, H, W), device="cuda")
+        dtick[c.submit_decode(sids[s], bits[i], imgs[i])] = i
+    res = _drain(c, len(dtick), timeout_s=120.0)
+    assert sorted(dtick[r["ticket"]] for r in res) == list(range(len(order)))
+    assert all(r["status"] == 0 for r in res)
+    c.close()
