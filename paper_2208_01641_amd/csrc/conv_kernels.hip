@@ -410,10 +410,69 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     constexpr int P = (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
+    // Gathered (NHWC) loaders walk this wave's chunks kslot, kslot + KSPLIT,
+    // ... with a cursor: the pixel offsets of a tap are computed once per tap
+    // and a chunk only adds its channel offset.  The load calls below come in
+    // exactly that chunk order.
+    constexpr bool kCursor = DT != DT_FP8 && LD != LD_RGB;
+    int cur_t = kslot / KC, cur_kc = kslot % KC;
+    long pixoff[NT];
+    bool pok[NT];
+    auto set_tap = [&](int t) {
+        const int tv = __builtin_amdgcn_readlane(tapv, t < ntaps ? t : 0);
+        const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
+            pok[nt] = t < ntaps && pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+            pixoff[nt] = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kg * KE;
+        }
+    };
+    if constexpr (kCursor) set_tap(cur_t);
+    auto load_cursor = [&](Frag (&A)[MT], BRaw (&B)[NT]) {
+      if constexpr (kCursor) {
+        const Elem* wp = wbase + ((long)cur_t * CoP + co0 + l16) * CIN + cur_kc * KCH + kg * KE;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            if constexpr (LD == LD_I8) {
+                const int8_t* src = pok[nt] ? static_cast<const int8_t*>(a.in) + pixoff[nt] + cur_kc * KCH
+                                            : static_cast<const int8_t*>(a.zero);
+                const float* mu = pok[nt] ? a.mu_in + cur_kc * KCH + kg * KE : static_cast<const float*>(a.zero);
+                I8Raw r;
+                if constexpr (KE == 4) {
+                    r.w[0] = *reinterpret_cast<const uint32_t*>(src);
+                } else {
+                    const uint2 u = *reinterpret_cast<const uint2*>(src);
+                    r.w[0] = u.x;
+                    r.w[1] = u.y;
+                }
+#pragma unroll
+                for (int e = 0; e < KE; e += 4) *reinterpret_cast<f4*>(&r.mu[e]) = *reinterpret_cast<const f4*>(mu + e);
+                B[nt] = r;
+            } else {
+                const Elem* src = pok[nt] ? static_cast<const Elem*>(a.in) + pixoff[nt] + cur_kc * KCH
+                                          : static_cast<const Elem*>(a.zero);
+                B[nt] = *reinterpret_cast<const Frag*>(src);
+            }
+        }
+        cur_kc += KSPLIT;
+        if (cur_kc >= KC) {
+            do {
+                cur_kc -= KC;
+                ++cur_t;
+            } while (cur_kc >= KC);
+            set_tap(cur_t);
+        }
+      }
+    };
     auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) {
         if constexpr (DT == DT_FP8) {
             loadA8(kk, A);
             loadB8(kk, B);
+        } else if constexpr (kCursor) {
+            load_cursor(A, B);
         } else {
             loadA(kk / KC, kk % KC, A);
             loadB(kk / KC, kk % KC, B);
