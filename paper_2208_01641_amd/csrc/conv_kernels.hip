@@ -411,11 +411,13 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
     // Gathered (NHWC) loaders walk this wave's chunks kslot, kslot + KSPLIT,
-    // ... with a cursor: the pixel offsets of a tap are computed once per tap
-    // and a chunk only adds its channel offset.  The load calls below come in
-    // exactly that chunk order.
+    // ... with a cursor, channel chunk outer and tap inner: all taps of one
+    // 16- (bf16: 32-) channel slice of the input window are consumed while the
+    // slice is in cache, so the input is fetched from HBM about once (tap-outer
+    // order re-reads the whole window once per tap).  The load calls below
+    // come in exactly the cursor's order.
     constexpr bool kCursor = DT != DT_FP8 && LD != LD_RGB;
-    int cur_t = kslot / KC, cur_kc = kslot % KC;
+    int cur_t = kslot % ntaps, cur_kc = kslot / ntaps;
     long pixoff[NT];
     bool pok[NT];
     auto set_tap = [&](int t) {
@@ -424,7 +426,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
-            pok[nt] = t < ntaps && pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
+            pok[nt] = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
             pixoff[nt] = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kg * KE;
         }
     };
@@ -457,14 +459,12 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 B[nt] = *reinterpret_cast<const Frag*>(src);
             }
         }
-        cur_kc += KSPLIT;
-        if (cur_kc >= KC) {
-            do {
-                cur_kc -= KC;
-                ++cur_t;
-            } while (cur_kc >= KC);
-            set_tap(cur_t);
+        cur_t += KSPLIT;
+        while (cur_t >= ntaps) {
+            cur_t -= ntaps;
+            ++cur_kc;
         }
+        set_tap(cur_t);
       }
     };
     auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) {
@@ -751,7 +751,7 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
     // e4m3 operands (precision form): g_a and g_s
-    LIC_KF(LIC_GA0, 128, 8, 2, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_KF(LIC_GA0, 128, 8, 1, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),
