@@ -35,6 +35,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
 {
@@ -150,7 +151,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     const int pix0 = (tile * PIXW + wave / KSPLIT) * (NT * 16);
     // without split-K there is no barrier, so idle waves may leave; with it,
     // every wave of the block has the same pix0 and leaves together
-    if (pix0 >= total) return;
+    // (the shared-weight path keeps idle waves: they take part in its barriers)
+    constexpr bool kALdsEarly = DT != DT_FP8 && LD != LD_RGB && KSPLIT == 1 && WAVES == 4 &&
+                                (EP == EP_GDN || EP == EP_IGDN) && MT % 4 == 0;
+    if (!kALdsEarly && pix0 >= total) return;
 
     int img[NT], gy[NT], gx[NT];
     bool pv[NT];
@@ -174,13 +178,13 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = b;
     }
 
-    auto loadA = [&](int t, int kc, Frag (&A)[MT]) {
+    auto loadA = [&](int t, int kc, Frag (&A)[MT]) __attribute__((always_inline)) {
         const Elem* wp = wbase + ((long)t * CoP + co0 + l16) * CIN + kc * KCH + kg * KE;
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
     };
 
-    auto loadB = [&](int t, int kc, BRaw (&B)[NT]) {
+    auto loadB = [&](int t, int kc, BRaw (&B)[NT]) __attribute__((always_inline)) {
         if constexpr (LD == LD_RGB) {
             // kk x kk taps over 3 NCHW channels flattened, k = (kk u + v) * 3 + c,
             // zero beyond 3 kk^2 (g_a's first layer: kk = 5, stride 2, pad 2)
@@ -257,7 +261,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     // the B operand of a ring entry: int8 symbols + offsets converted, |y|
     // taken for the h_a input, everything else as loaded
-    auto cook = [&](const BRaw& r) -> Frag {
+    auto cook = [&](const BRaw& r) __attribute__((always_inline)) -> Frag {
         if constexpr (LD == LD_I8 && DT != DT_FP8) {
             Frag v;
 #pragma unroll
@@ -278,7 +282,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         }
     };
 
-    auto compute = [&](const Frag (&A)[MT], const BRaw (&Braw)[NT]) {
+    auto compute = [&](const Frag (&A)[MT], const BRaw (&Braw)[NT]) __attribute__((always_inline)) {
         Frag B[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) B[nt] = cook(Braw[nt]);
@@ -307,7 +311,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     // DT_FP8: chunk kc of the flattened (tap, channel) axis; this lane group
     // takes channels c .. c + 31 of tap t (t >= ntaps: past the end, zeros)
-    auto loadA8 = [&](int kc, Frag (&A)[MT]) {
+    auto loadA8 = [&](int kc, Frag (&A)[MT]) __attribute__((always_inline)) {
         const int f = kc * KCH + kg * KE;
         const int t = f / CIN, c = f - (f / CIN) * CIN;
 #pragma unroll
@@ -321,7 +325,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     auto pack4 = [](float v0, float v1, float v2, float v3) -> int {
         return (int)(e4m3x2(v0, v1) | (e4m3x2(v2, v3) << 16));
     };
-    auto loadB8 = [&](int kc, Frag (&B)[NT]) {
+    auto loadB8 = [&](int kc, Frag (&B)[NT]) __attribute__((always_inline)) {
         const int f = kc * KCH + kg * KE;
         const int t = f / CIN, c = f - (f / CIN) * CIN;
 #pragma unroll
@@ -385,7 +389,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     };
 
     // stores 4 consecutive channels of one pixel in the activation storage type
-    auto store_act = [&](long idx, const f4& y) {
+    auto store_act = [&](long idx, const f4& y) __attribute__((always_inline)) {
         if constexpr (DT == DT_F32) {
             *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
         } else if constexpr (DT == DT_FP8) {
@@ -407,7 +411,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     constexpr int STAGE = (MT * (int)sizeof(Frag) + NT * (int)sizeof(BRaw)) / 4;   // VGPRs per chunk buffer
     constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
     // (the image loader has only a handful of chunks: keep its ring short)
-    constexpr int P = (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
+    constexpr int P = kALdsEarly ? 3
+                  : (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
     // Gathered (NHWC) loaders walk this wave's chunks kslot, kslot + KSPLIT,
@@ -420,7 +425,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     int cur_t = kslot % ntaps, cur_kc = kslot / ntaps;
     long pixoff[NT];
     bool pok[NT];
-    auto set_tap = [&](int t) {
+    auto set_tap = [&](int t) __attribute__((always_inline)) {
         const int tv = __builtin_amdgcn_readlane(tapv, t < ntaps ? t : 0);
         const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
 #pragma unroll
@@ -431,11 +436,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         }
     };
     if constexpr (kCursor) set_tap(cur_t);
-    auto load_cursor = [&](Frag (&A)[MT], BRaw (&B)[NT]) {
+    auto cursor_loadB = [&](BRaw (&B)[NT]) __attribute__((always_inline)) {
       if constexpr (kCursor) {
-        const Elem* wp = wbase + ((long)cur_t * CoP + co0 + l16) * CIN + cur_kc * KCH + kg * KE;
-#pragma unroll
-        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if constexpr (LD == LD_I8) {
@@ -467,7 +469,15 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         set_tap(cur_t);
       }
     };
-    auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) {
+    auto load_cursor = [&](Frag (&A)[MT], BRaw (&B)[NT]) __attribute__((always_inline)) {
+        if constexpr (kCursor) {
+            const Elem* wp = wbase + ((long)cur_t * CoP + co0 + l16) * CIN + cur_kc * KCH + kg * KE;
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
+            cursor_loadB(B);
+        }
+    };
+    auto load = [&](int kk, Frag (&A)[MT], BRaw (&B)[NT]) __attribute__((always_inline)) {
         if constexpr (DT == DT_FP8) {
             loadA8(kk, A);
             loadB8(kk, B);
@@ -478,8 +488,90 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             loadB(kk / KC, kk % KC, B);
         }
     };
-    Frag Ab[P][MT];
-    BRaw Bb[P][NT];
+    // Shared weights (GDN layers, one pixel tile per wave, no split-K): the
+    // four waves of a block need the same weight rows for every chunk, so the
+    // block stages each chunk's weight tile in LDS once (two 16-byte pieces
+    // per thread) instead of every wave fetching it: a 3-stage LDS ring,
+    // filled two chunks ahead from registers loaded two chunks before that,
+    // one barrier per chunk.  The pixel operands keep their per-wave ring.
+    constexpr bool kALds = kALdsEarly;
+    if constexpr (kALds) {
+        static_assert(P == 3, "the shared-weight loop is written for a 3-deep ring");
+        constexpr int NPIECE = MT / 4;                      // 16-byte pieces per thread per chunk
+        constexpr int AROW = 20;                            // LDS row pitch in dwords (64 + 16 bytes)
+        constexpr int ROWS = MT * 16;
+        __shared__ __attribute__((aligned(16))) uint32_t As[3 * ROWS * AROW];
+        const int tid = threadIdx.x;
+        int a_t = 0, a_kc = 0;
+        auto a_gload = [&](u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < NPIECE; ++i) {
+                const int q = tid + i * 256, row = q >> 2, c16 = q & 3;
+                const Elem* src = wbase + ((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH + c16 * (16 / (int)sizeof(Elem));
+                r[i] = *reinterpret_cast<const u32x4*>(src);
+            }
+            if (++a_t == ntaps) {
+                a_t = 0;
+                ++a_kc;
+            }
+        };
+        auto a_store = [&](int stage, const u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < NPIECE; ++i) {
+                const int q = tid + i * 256, row = q >> 2, c16 = q & 3;
+                *reinterpret_cast<u32x4*>(&As[(stage * ROWS + row) * AROW + c16 * 4]) = r[i];
+            }
+        };
+        auto a_frag = [&](int stage, Frag (&A)[MT]) __attribute__((always_inline)) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const u32x4 u = *reinterpret_cast<const u32x4*>(&As[(stage * ROWS + mt * 16 + l16) * AROW + kg * 4]);
+                A[mt] = __builtin_bit_cast(Frag, u);
+            }
+        };
+        BRaw Bb[P][NT];
+        u32x4 ra[3][NPIECE];
+        // prologue: weights of chunks 0..2 in registers, 0 and 1 in LDS, 3 in flight
+        if (0 < nk) a_gload(ra[0]);
+        if (1 < nk) a_gload(ra[1]);
+        if (2 < nk) a_gload(ra[2]);
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j)
+            if (j < nk) cursor_loadB(Bb[j]);
+        if (0 < nk) a_store(0, ra[0]);
+        if (1 < nk) a_store(1, ra[1]);
+        if (3 < nk) a_gload(ra[0]);
+        __syncthreads();
+        // chunk k: weights in stage k % 3 (register set k % 3), pixels in Bb[k % 3]
+        // (j is a compile-time constant so that every ring index is static)
+        auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;
+            if (!guard || k + P - 1 < nk) cursor_loadB(Bb[(j + P - 1) % P]);
+            Frag A[MT];
+            a_frag(j, A);
+            compute(A, Bb[j]);
+            if (!guard || k + 2 < nk) a_store((j + 2) % 3, ra[(j + 2) % 3]);
+            if (!guard || k + 4 < nk) a_gload(ra[(j + 1) % 3]);
+            __syncthreads();
+        };
+        int k0 = 0;
+        using J0 = std::integral_constant<int, 0>;
+        using J1 = std::integral_constant<int, 1>;
+        using J2 = std::integral_constant<int, 2>;
+        for (; k0 + 6 < nk; k0 += 3) {
+            step(k0, J0{}, false);
+            step(k0 + 1, J1{}, false);
+            step(k0 + 2, J2{}, false);
+        }
+        for (; k0 < nk; k0 += 3) {
+            step(k0, J0{}, true);
+            if (k0 + 1 < nk) step(k0 + 1, J1{}, true);
+            if (k0 + 2 < nk) step(k0 + 2, J2{}, true);
+        }
+    }
+    Frag Ab[kALds ? 1 : P][MT];
+    BRaw Bb[kALds ? 1 : P][NT];
+    if constexpr (!kALds) {
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
         if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
@@ -501,6 +593,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             if (k + P - 1 < nk) load(kslot + (k + P - 1) * KSPLIT, Ab[(j + P - 1) % P], Bb[(j + P - 1) % P]);
             compute(Ab[j], Bb[j]);
         }
+    }
     }
 
     if constexpr (KSPLIT > 1) {
@@ -751,7 +844,7 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
     // e4m3 operands (precision form): g_a and g_s
-    LIC_KF(LIC_GA0, 128, 8, 1, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_KF(LIC_GA0, 128, 8, 2, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),

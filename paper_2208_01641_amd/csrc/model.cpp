@@ -444,8 +444,7 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
     const long pixels = (long)a.n * a.Hg * a.Wg;
     if (L.ep == EP_GDN || L.ep == EP_IGDN) {
         key.mt = L.cop / 16;
-        // (the e4m3 image loader converts 32 values per lane: one pixel group)
-        key.nt = (key.mt <= 8 && !(L.dt == DT_FP8 && L.ld == LD_RGB)) ? 2 : 1;
+        key.nt = key.mt <= 8 ? 2 : 1;
         key.waves = 4;
         a.ncog = 1;
         // fewer than one wave per SIMD (1024 on the chip) from the pixel

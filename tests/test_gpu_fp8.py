@@ -73,6 +73,9 @@ def act(t):
     return np.transpose(e4m3_decode(t[0].cpu().numpy()) / Q, (2, 0, 1))
 
 
+# (N, M, H, W): both channel widths of the transforms, ragged sizes included
+CASES = [(128, 192, 128, 192), (128, 192, 200, 328), (192, 320, 136, 200)]
+
 @pytest.fixture(scope="module")
 def torch_dev():
     import torch
@@ -80,14 +83,14 @@ def torch_dev():
     return torch
 
 
-@pytest.mark.parametrize("H,W", [(128, 192), (200, 328)])
-def test_fp8_analysis_layers(torch_dev, H, W):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_fp8_analysis_layers(torch_dev, N, M, H, W):
     torch = torch_dev
-    c, m = make_codec(1, 128, 192, gamma="dense", precision=2, max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(1, N, M, gamma="dense", precision=2, max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     x = synth.frame_sinusoid(H, W, t=2)
     xd = torch.from_numpy(x)[None].cuda()
-    a = torch.empty((1,) + layer_out_shape("GA0", H, W, 128, 192), device="cuda", dtype=torch.uint8)
+    a = torch.empty((1,) + layer_out_shape("GA0", H, W, N, M), device="cuda", dtype=torch.uint8)
     c.run_layer("GA0", 1, H, W, xd, a)
     ref = oracle.gdn(oracle.conv2d(e4m3(oracle.pad64(x)), w_fp8(P["ga0.w"], "conv"), P["ga0.b"], 2, 2),
                      P["ga0.beta"], P["ga0.gamma"])
@@ -95,13 +98,13 @@ def test_fp8_analysis_layers(torch_dev, H, W):
     assert rel_err(act(a), ref) < FP8_OUT_TOL
     prev = a
     for i, L in ((1, "GA1"), (2, "GA2")):
-        o = torch.empty((1,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=torch.uint8)
+        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda", dtype=torch.uint8)
         c.run_layer(L, 1, H, W, prev, o)
         ref = oracle.gdn(oracle.conv2d(act(prev), w_fp8(P[f"ga{i}.w"], "conv"), P[f"ga{i}.b"], 2, 2),
                          P[f"ga{i}.beta"], P[f"ga{i}.gamma"])
         assert rel_err(act(o), ref) < FP8_OUT_TOL, L
         prev = o
-    y = torch.empty((1,) + layer_out_shape("GA3", H, W, 128, 192), device="cuda")
+    y = torch.empty((1,) + layer_out_shape("GA3", H, W, N, M), device="cuda")
     sy = torch.empty_like(y, dtype=torch.int8)
     c.run_layer("GA3", 1, H, W, prev, y, sy)
     yref = oracle.conv2d(act(prev), w_fp8(P["ga3.w"], "conv"), P["ga3.b"], 2, 2)
@@ -111,18 +114,18 @@ def test_fp8_analysis_layers(torch_dev, H, W):
     c.close()
 
 
-@pytest.mark.parametrize("H,W", [(128, 192), (200, 328)])
-def test_fp8_synthesis_layers(torch_dev, H, W):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_fp8_synthesis_layers(torch_dev, N, M, H, W):
     torch = torch_dev
-    c, m = make_codec(1, 128, 192, gamma="dense", precision=2, max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(1, N, M, gamma="dense", precision=2, max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     rng = np.random.default_rng(H + W)
-    d = layer_out_shape("GA3", H, W, 128, 192)
-    sym = np.clip(np.rint(rng.normal(0, 1.5, (192, d[0], d[1]))), -64, 64).astype(np.int8)
+    d = layer_out_shape("GA3", H, W, N, M)
+    sym = np.clip(np.rint(rng.normal(0, 1.5, (M, d[0], d[1]))), -64, 64).astype(np.int8)
     prev = torch.from_numpy(np.ascontiguousarray(np.transpose(sym, (1, 2, 0)))[None]).cuda()
     src = e4m3(sym.astype(np.float64))
     for i, L in ((0, "GS0"), (1, "GS1"), (2, "GS2")):
-        o = torch.empty((1,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=torch.uint8)
+        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda", dtype=torch.uint8)
         c.run_layer(L, 1, H, W, prev, o)
         ref = oracle.gdn(oracle.deconv2d(src, w_fp8(P[f"gs{i}.w"], "deconv"), P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)

@@ -20,6 +20,9 @@ from gpu_util import boundary_mismatches, chw, index_mismatches, layer_out_shape
 pytestmark = pytest.mark.gpu
 
 SIZES = [(128, 128), (200, 328)]
+# (N, M, H, W): the two channel widths of the transforms (N=128 M=192 and
+# N=192 M=320, the larger of which uses 12-row-block weight tiles)
+CASES = [(128, 192, 128, 128), (128, 192, 200, 328), (192, 320, 136, 200)]
 
 
 @pytest.fixture(scope="module")
@@ -34,28 +37,28 @@ def _empty(torch, shape, dtype=None):
 
 
 @pytest.mark.parametrize("gamma", ["diag", "dense"])
-@pytest.mark.parametrize("H,W", SIZES)
-def test_analysis_layers(torch_dev, H, W, gamma):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_analysis_layers(torch_dev, N, M, H, W, gamma):
     torch = torch_dev
-    c, m = make_codec(1, 128, 192, gamma=gamma, max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(1, N, M, gamma=gamma, max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     x = synth.frame_sinusoid(H, W, t=3)
     xd = torch.from_numpy(x)[None].cuda()
     # GA0: NCHW image (padding and layout change fused in the loader)
-    out = _empty(torch, layer_out_shape("GA0", H, W, 128, 192))
+    out = _empty(torch, layer_out_shape("GA0", H, W, N, M))
     c.run_layer("GA0", 1, H, W, xd, out)
     ref = oracle.gdn(oracle.conv2d(oracle.pad64(x), P["ga0.w"], P["ga0.b"], 2, 2), P["ga0.beta"], P["ga0.gamma"])
     assert rel_err(chw(out), ref) < 1e-4
     prev = out
     for i, L in ((1, "GA1"), (2, "GA2")):
-        out = _empty(torch, layer_out_shape(L, H, W, 128, 192))
+        out = _empty(torch, layer_out_shape(L, H, W, N, M))
         c.run_layer(L, 1, H, W, prev, out)
         ref = oracle.gdn(oracle.conv2d(chw(prev), P[f"ga{i}.w"], P[f"ga{i}.b"], 2, 2),
                          P[f"ga{i}.beta"], P[f"ga{i}.gamma"])
         assert rel_err(chw(out), ref) < 1e-4, L
         prev = out
-    y = _empty(torch, layer_out_shape("GA3", H, W, 128, 192))
-    sym = _empty(torch, layer_out_shape("GA3", H, W, 128, 192), torch.int8)
+    y = _empty(torch, layer_out_shape("GA3", H, W, N, M))
+    sym = _empty(torch, layer_out_shape("GA3", H, W, N, M), torch.int8)
     c.run_layer("GA3", 1, H, W, prev, y, sym)
     yref = oracle.conv2d(chw(prev), P["ga3.w"], P["ga3.b"], 2, 2)
     assert rel_err(chw(y), yref) < 1e-4
@@ -120,20 +123,20 @@ def test_hyper_layers(torch_dev, H, W, hs_out):
 
 
 @pytest.mark.parametrize("kind", [1, 0])
-@pytest.mark.parametrize("H,W", SIZES)
-def test_synthesis_layers(torch_dev, H, W, kind):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_synthesis_layers(torch_dev, N, M, H, W, kind):
     torch = torch_dev
-    c, m = make_codec(kind, 128, 192, gamma="dense", max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(kind, N, M, gamma="dense", max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     rng = np.random.default_rng(7 + H)
-    d = layer_out_shape("GA3", H, W, 128, 192)
-    sym = np.clip(np.rint(rng.normal(0, 1.5, (192, d[0], d[1]))), -64, 64).astype(np.int8)
-    mu = (m.medians if kind == 0 else np.zeros(192, np.float32))[:, None, None].astype(np.float64)
+    d = layer_out_shape("GA3", H, W, N, M)
+    sym = np.clip(np.rint(rng.normal(0, 1.5, (M, d[0], d[1]))), -64, 64).astype(np.int8)
+    mu = (m.medians if kind == 0 else np.zeros(M, np.float32))[:, None, None].astype(np.float64)
     yhat = sym.astype(np.float64) + mu
     prev = to_nhwc(sym, "cuda")
     src = yhat
     for i, L in ((0, "GS0"), (1, "GS1"), (2, "GS2")):
-        out = _empty(torch, layer_out_shape(L, H, W, 128, 192))
+        out = _empty(torch, layer_out_shape(L, H, W, N, M))
         c.run_layer(L, 1, H, W, prev, out)
         ref = oracle.gdn(oracle.deconv2d(src, P[f"gs{i}.w"], P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)

@@ -19,6 +19,8 @@ from test_gpu_codec import _expected_stream
 pytestmark = pytest.mark.gpu
 
 BF16_OUT_TOL = 2.0 ** -8
+# (N, M, H, W): both channel widths of the transforms, ragged sizes included
+CASES = [(128, 192, 128, 192), (128, 192, 200, 328), (192, 320, 136, 200)]
 
 
 def bf16(a):
@@ -40,27 +42,27 @@ def torch_dev():
     return torch
 
 
-@pytest.mark.parametrize("H,W", [(128, 192), (200, 328)])
-def test_bf16_analysis_layers(torch_dev, H, W):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_bf16_analysis_layers(torch_dev, N, M, H, W):
     torch = torch_dev
-    c, m = make_codec(1, 128, 192, gamma="dense", precision=1, max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(1, N, M, gamma="dense", precision=1, max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     x = synth.frame_sinusoid(H, W, t=2)
     xd = torch.from_numpy(x)[None].cuda()
-    a = torch.empty((1,) + layer_out_shape("GA0", H, W, 128, 192), device="cuda", dtype=torch.bfloat16)
+    a = torch.empty((1,) + layer_out_shape("GA0", H, W, N, M), device="cuda", dtype=torch.bfloat16)
     c.run_layer("GA0", 1, H, W, xd, a)
     ref = oracle.gdn(oracle.conv2d(bf16(oracle.pad64(x)), bf16(P["ga0.w"]), P["ga0.b"], 2, 2),
                      P["ga0.beta"], P["ga0.gamma"])
     assert rel_err(chw_any(a), ref) < BF16_OUT_TOL
     prev = a
     for i, L in ((1, "GA1"), (2, "GA2")):
-        o = torch.empty((1,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=torch.bfloat16)
+        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda", dtype=torch.bfloat16)
         c.run_layer(L, 1, H, W, prev, o)
         ref = oracle.gdn(oracle.conv2d(chw_any(prev), bf16(P[f"ga{i}.w"]), P[f"ga{i}.b"], 2, 2),
                          P[f"ga{i}.beta"], P[f"ga{i}.gamma"])
         assert rel_err(chw_any(o), ref) < BF16_OUT_TOL, L
         prev = o
-    y = torch.empty((1,) + layer_out_shape("GA3", H, W, 128, 192), device="cuda")
+    y = torch.empty((1,) + layer_out_shape("GA3", H, W, N, M), device="cuda")
     sy = torch.empty_like(y, dtype=torch.int8)
     c.run_layer("GA3", 1, H, W, prev, y, sy)
     yref = oracle.conv2d(chw_any(prev), bf16(P["ga3.w"]), P["ga3.b"], 2, 2)
@@ -70,18 +72,18 @@ def test_bf16_analysis_layers(torch_dev, H, W):
     c.close()
 
 
-@pytest.mark.parametrize("H,W", [(128, 192), (200, 328)])
-def test_bf16_synthesis_layers(torch_dev, H, W):
+@pytest.mark.parametrize("N,M,H,W", CASES)
+def test_bf16_synthesis_layers(torch_dev, N, M, H, W):
     torch = torch_dev
-    c, m = make_codec(1, 128, 192, gamma="dense", precision=1, max_h=H, max_w=W, max_in_flight=1)
+    c, m = make_codec(1, N, M, gamma="dense", precision=1, max_h=H, max_w=W, max_in_flight=1)
     P = m.P
     rng = np.random.default_rng(H + W)
-    d = layer_out_shape("GA3", H, W, 128, 192)
-    sym = np.clip(np.rint(rng.normal(0, 1.5, (192, d[0], d[1]))), -64, 64).astype(np.int8)
+    d = layer_out_shape("GA3", H, W, N, M)
+    sym = np.clip(np.rint(rng.normal(0, 1.5, (M, d[0], d[1]))), -64, 64).astype(np.int8)
     prev = torch.from_numpy(np.ascontiguousarray(np.transpose(sym, (1, 2, 0)))[None]).cuda()
     src = sym.astype(np.float64)
     for i, L in ((0, "GS0"), (1, "GS1"), (2, "GS2")):
-        o = torch.empty((1,) + layer_out_shape(L, H, W, 128, 192), device="cuda", dtype=torch.bfloat16)
+        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda", dtype=torch.bfloat16)
         c.run_layer(L, 1, H, W, prev, o)
         ref = oracle.gdn(oracle.deconv2d(src, bf16(P[f"gs{i}.w"]), P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
