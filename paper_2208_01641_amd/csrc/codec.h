@@ -36,7 +36,7 @@ struct LayerGPU {
     uint8_t* d_w = nullptr;            // packed weights (float or bf16)
     float* d_bias = nullptr;
     float* d_rscale = nullptr;         // e4m3 form: per packed row, weight scale x input scale
-    float* d_gamma = nullptr;
+    uint16_t* d_gsplit = nullptr;   // gamma as bf16 parts (layout in ConvArgs::gsplit)
     float* d_beta = nullptr;
     const float* d_qmu = nullptr;      // EP_QUANT offsets
     const float* d_mu_in = nullptr;    // LD_I8 offsets
@@ -45,6 +45,7 @@ struct LayerGPU {
 // e4m3 activations between layers hold kActQ x the value (|value| <= 56 fits)
 constexpr float kActQ = 8.0f;
 uint8_t e4m3_rne(float f);
+std::vector<uint16_t> gdn_gamma_split(const std::vector<double>& gamma, int co);
 
 struct Geo {
     int Hin, Win, Hg, Wg, s_in, Hout, Wout, s_out;

@@ -54,7 +54,8 @@ struct ConvArgs {
     const void* zero;        // >= 64 zero bytes: the source of out-of-image reads
     const float* bias;       // [CoP]
     const float* mu_in;      // LD_I8 offsets [CIN]
-    const float* gamma;      // GDN [Co][Co]
+    const void* gsplit;      // GDN gamma [Co][Co] as three bf16 parts, [part][r][p][kg][i] of
+                             // shape [3][Co][Co/32][4][8]: part of gamma[r][(2p + i/4) 16 + 4 kg + i%4]
     const float* beta;       // GDN [Co]
     const float* qmu;        // EP_QUANT offsets [Co]
     const float* thr;        // EP_INDEX thresholds [63]

@@ -151,10 +151,18 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     const int pix0 = (tile * PIXW + wave / KSPLIT) * (NT * 16);
     // without split-K there is no barrier, so idle waves may leave; with it,
     // every wave of the block has the same pix0 and leaves together
-    // (the shared-weight path keeps idle waves: they take part in its barriers)
-    constexpr bool kALdsEarly = DT != DT_FP8 && LD != LD_RGB && KSPLIT == 1 && WAVES == 4 &&
-                                (EP == EP_GDN || EP == EP_IGDN) && MT % 4 == 0;
-    if (!kALdsEarly && pix0 >= total) return;
+    // (GDN blocks of four unsplit waves keep idle waves: they take part in the
+    // barriers of the shared weight and gamma staging)
+    constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
+    constexpr bool kALdsEarly = kGLds && DT != DT_FP8 && LD != LD_RGB && MT % 4 == 0;
+    if (!kGLds && pix0 >= total) return;
+    // one LDS buffer for the staged weight ring of the K loop and, after it,
+    // the staged gamma slices of the GDN epilogue
+    constexpr int kGP = DT == DT_F32 ? 3 : 2;                   // bf16 parts of gamma
+    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : 0;
+    constexpr int kGWords = kGLds ? 2 * kGP * MT * 16 * 16 : 0;
+    constexpr int kSmemWords = (kAWords > kGWords ? kAWords : kGWords) > 0 ? (kAWords > kGWords ? kAWords : kGWords) : 4;
+    __shared__ __attribute__((aligned(16))) uint32_t smem[kSmemWords];
 
     int img[NT], gy[NT], gx[NT];
     bool pv[NT];
@@ -500,7 +508,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         constexpr int NPIECE = MT / 4;                      // 16-byte pieces per thread per chunk
         constexpr int AROW = 20;                            // LDS row pitch in dwords (64 + 16 bytes)
         constexpr int ROWS = MT * 16;
-        __shared__ __attribute__((aligned(16))) uint32_t As[3 * ROWS * AROW];
+        uint32_t* const As = smem;                          // [3][ROWS][AROW]
+        static_assert(3 * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
         const int tid = threadIdx.x;
         int a_t = 0, a_kc = 0;
         auto a_gload = [&](u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
@@ -637,8 +646,22 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     }
 
     if constexpr (EP == EP_GDN || EP == EP_IGDN) {
-        // n = beta + gamma (x*x): [Co x Co] x [Co x pixels] on MFMA, K chunk
-        // kc2 of the contraction is exactly this lane's accumulator row block.
+        // n = beta + gamma (x*x): [Co x Co] x [Co x pixels] on the bf16 matrix
+        // cores with FP32 accumulation.  x*x and gamma are each split into
+        // bf16 parts rounded to nearest (v = v0 + v1 + v2 + e, |e| <= 2^-27 |v|;
+        // gamma's parts are precomputed); the products of parts whose orders
+        // sum to at most GP - 1 are kept: six for the FP32 form (relative error
+        // of n about 2^-25, the level of FP32 rounding), three for the bf16 and
+        // e4m3 forms (about 2^-16, far below their bf16 / e4m3 outputs).  Every
+        // product of bf16 parts is exact in FP32.  One K chunk of 32 channels
+        // is the row-block pair (2p, 2p+1) of the accumulators: slot i of lane
+        // group kg holds channel (2p + i/4) 16 + 4 kg + i%4, which is exactly
+        // this lane's accumulator element, and gamma's parts are stored in
+        // the same channel order.
+        static_assert(MT % 2 == 0, "GDN rows come in 32-channel pairs");
+        constexpr int GP = kGP;                     // bf16 parts per operand
+        const bf16x8* __restrict__ gsp = static_cast<const bf16x8*>(a.gsplit);
+        constexpr int NPAIR = MT / 2;
         f4 nacc[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
@@ -646,20 +669,97 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) nacc[mt][nt] = b;
         }
+        // Whole blocks stage gamma one 32-channel slice (all rows, GP parts)
+        // at a time in LDS, double-buffered: slice p + 1 is fetched into
+        // registers while slice p feeds the matrix cores, so the block reads
+        // gamma from L2 once instead of once per wave.  Slice layout: 16-byte
+        // chunk (g Co + r) 4 + kg = gamma parts of row r, lane group kg.
+        constexpr int SCH = GP * MT * 16 * 4;       // 16-byte chunks per slice
+        constexpr int SPT = kGLds ? (SCH + 255) / 256 : 1;
+        u32x4* const gbuf = reinterpret_cast<u32x4*>(smem);
+        u32x4 gst[SPT];
+        auto g_fetch = [&](int p) __attribute__((always_inline)) {
 #pragma unroll
-        for (int kc2 = 0; kc2 < MT; ++kc2) {
-            f4 G[MT], X[NT];
+            for (int i = 0; i < SPT; ++i) {
+                const int q = threadIdx.x + i * 256;
+                if (SCH % 256 == 0 || q < SCH) {
+                    const int gr = q >> 2, kq = q & 3;         // gr = g Co + r
+                    gst[i] = *reinterpret_cast<const u32x4*>(gsp + ((long)gr * NPAIR + p) * 4 + kq);
+                }
+            }
+        };
+        auto g_put = [&](int buf) __attribute__((always_inline)) {
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt)
-                G[mt] = *reinterpret_cast<const f4*>(a.gamma + (long)(mt * 16 + l16) * a.Co + kc2 * 16 + kg * 4);
+            for (int i = 0; i < SPT; ++i) {
+                const int q = threadIdx.x + i * 256;
+                if (SCH % 256 == 0 || q < SCH) gbuf[buf * SCH + q] = gst[i];
+            }
+        };
+        if constexpr (kGLds) {
+            static_assert(2 * SCH * 4 <= kSmemWords, "two gamma slices fit the LDS buffer");
+            g_fetch(0);
+            __syncthreads();                        // the K loop's last LDS reads are done
+            g_put(0);
+            __syncthreads();
+        }
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) X[nt] = acc[kc2][nt] * acc[kc2][nt];
+        for (int p = 0; p < NPAIR; ++p) {
+            if constexpr (kGLds) {
+                if (p + 1 < NPAIR) g_fetch(p + 1);
+            }
+            bf16x8 S[GP][NT];
 #pragma unroll
-            for (int e = 0; e < 4; ++e)
+            for (int nt = 0; nt < NT; ++nt) {
+                uint32_t sb[GP][8];
 #pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
+                for (int i = 0; i < 8; ++i) {
+                    const float x = acc[2 * p + i / 4][nt][i % 4];
+                    float r = x * x;
 #pragma unroll
-                    for (int nt = 0; nt < NT; ++nt) nacc[mt][nt] = mfma16x16x4(G[mt][e], X[nt][e], nacc[mt][nt]);
+                    for (int g = 0; g < GP; ++g) {
+                        uint32_t u = __float_as_uint(r);
+                        u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
+                        sb[g][i] = u;
+                        r -= __uint_as_float(u);        // exact: u is r to 8 bits
+                    }
+                }
+#pragma unroll
+                for (int g = 0; g < GP; ++g) {
+                    u32x4 w;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j) w[j] = (sb[g][2 * j] >> 16) | sb[g][2 * j + 1];
+                    S[g][nt] = __builtin_bit_cast(bf16x8, w);
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                bf16x8 G[GP];
+#pragma unroll
+                for (int g = 0; g < GP; ++g) {
+                    if constexpr (kGLds)
+                        G[g] = __builtin_bit_cast(bf16x8, gbuf[(p & 1) * SCH + (g * MT * 16 + mt * 16 + l16) * 4 + kg]);
+                    else
+                        G[g] = gsp[((long)(g * a.Co + mt * 16 + l16) * NPAIR + p) * 4 + kg];
+                }
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) {
+                    // smallest products first
+                    if constexpr (GP == 3) {
+                        nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[0], S[2][nt], nacc[mt][nt], 0, 0, 0);
+                        nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[1], S[1][nt], nacc[mt][nt], 0, 0, 0);
+                        nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[2], S[0][nt], nacc[mt][nt], 0, 0, 0);
+                    }
+                    nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[0], S[1][nt], nacc[mt][nt], 0, 0, 0);
+                    nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[1], S[0][nt], nacc[mt][nt], 0, 0, 0);
+                    nacc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(G[0], S[0][nt], nacc[mt][nt], 0, 0, 0);
+                }
+            }
+            if constexpr (kGLds) {
+                if (p + 1 < NPAIR) {
+                    g_put((p + 1) & 1);             // that buffer's last reader was slice p - 1
+                    __syncthreads();
+                }
+            }
         }
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -668,8 +768,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                 f4 y;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    const float r = sqrtf(nacc[mt][nt][i]);
-                    y[i] = (EP == EP_GDN) ? acc[mt][nt][i] / r : acc[mt][nt][i] * r;
+                    // GDN: x times the hardware reciprocal square root (within
+                    // about one ulp; n >= beta > 0), IGDN: x sqrt(n)
+                    y[i] = (EP == EP_GDN) ? acc[mt][nt][i] * __builtin_amdgcn_rsqf(nacc[mt][nt][i])
+                                          : acc[mt][nt][i] * sqrtf(nacc[mt][nt][i]);
                 }
                 if (pv[nt]) store_act(obase[nt] + mt * 16 + kg * 4, y);
             }

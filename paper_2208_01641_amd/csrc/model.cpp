@@ -105,6 +105,33 @@ uint16_t bf16_rne(float f)
     return (uint16_t)(u >> 16);
 }
 
+// GDN gamma [co][co] (row-major, FP64 from the weight blob, used as FP32)
+// as three bf16 parts g0 + g1 + g2, each rounded to nearest from what the
+// previous parts leave (remainders are exact in FP32), laid out for the
+// GDN epilogue: part k of gamma[r][(2p + i/4) 16 + 4 kg + i%4] at
+// (((k co + r) (co/32) + p) 4 + kg) 8 + i.
+std::vector<uint16_t> gdn_gamma_split(const std::vector<double>& gamma, int co)
+{
+    const int npair = co / 32;
+    std::vector<uint16_t> out((size_t)3 * co * co);
+    for (int r = 0; r < co; ++r)
+        for (int p = 0; p < npair; ++p)
+            for (int kg = 0; kg < 4; ++kg)
+                for (int i = 0; i < 8; ++i) {
+                    const int c = (2 * p + i / 4) * 16 + 4 * kg + i % 4;
+                    float rem = (float)gamma[(size_t)r * co + c];
+                    for (int k = 0; k < 3; ++k) {
+                        const uint16_t h = bf16_rne(rem);
+                        out[((((size_t)k * co + r) * npair + p) * 4 + kg) * 8 + i] = h;
+                        const uint32_t u = (uint32_t)h << 16;
+                        float hv;
+                        memcpy(&hv, &u, 4);
+                        rem -= hv;
+                    }
+                }
+    return out;
+}
+
 // OCP e4m3 (1 sign, 4 exponent bits with bias 7, 3 mantissa bits; largest
 // finite 448, subnormal step 2^-9, no infinities) of f, rounding to nearest
 // even and saturating at +-448.
@@ -356,12 +383,13 @@ int Codec::build_layers(const ParamMap& P)
                 err = std::string("weight blob: GDN parameters missing in ") + sp.name;
                 return LIC_E_MODEL;
             }
-            std::vector<float> g(git->second.second.begin(), git->second.second.end());
+            if (co % 32 != 0) { err = std::string("GDN layers need a multiple of 32 channels: ") + sp.name; return LIC_E_MODEL; }
+            const std::vector<uint16_t> g = gdn_gamma_split(git->second.second, co);
             std::vector<float> be(beit->second.second.begin(), beit->second.second.end());
-            L.d_gamma = (float*)dev_alloc(g.size() * sizeof(float));
+            L.d_gsplit = (uint16_t*)dev_alloc(g.size() * sizeof(uint16_t));
             L.d_beta = (float*)dev_alloc(be.size() * sizeof(float));
-            if (!L.d_gamma || !L.d_beta) { err = "device allocation failed"; return LIC_E_NOMEM; }
-            HIP_TRY(hipMemcpy(L.d_gamma, g.data(), g.size() * sizeof(float), hipMemcpyHostToDevice));
+            if (!L.d_gsplit || !L.d_beta) { err = "device allocation failed"; return LIC_E_NOMEM; }
+            HIP_TRY(hipMemcpy(L.d_gsplit, g.data(), g.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
             HIP_TRY(hipMemcpy(L.d_beta, be.data(), be.size() * sizeof(float), hipMemcpyHostToDevice));
         }
         // offsets: quantisation of y (factorized: channel medians; hyperprior: 0)
@@ -411,7 +439,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.zero = d_zero;
     a.bias = L.d_bias;
     a.mu_in = L.d_mu_in;
-    a.gamma = L.d_gamma;
+    a.gsplit = L.d_gsplit;
     a.beta = L.d_beta;
     a.qmu = L.d_qmu;
     a.thr = d_thr;
