@@ -30,7 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "720p hyperprior enc+dec frames/s + p99 ms; BF16/FP8 vs FP32 at fixed PSNR"
-PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0}   # MI355X dense matrix peaks
+# MI355X dense matrix peaks per operand form of a kernel's GEMM; the
+# split-FP32 form issues six bf16 products per FP32 product, so its ceiling
+# in FP32 FLOP/s is the bf16 peak / 6
+PEAK_TFLOPS = {"f32": 157.3, "bf16": 2500.0, "fp8": 5000.0, "f32x": 2500.0 / 6}
+PEAK_BASIS = {"f32": "FP32 matrix cores", "bf16": "bf16 matrix cores", "fp8": "fp8 matrix cores",
+              "f32x": "bf16 matrix cores / 6 (six bf16 products per FP32 product)"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_01641_amd", "csrc", "conv_kernels.hip")
 LAYERS = ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3")
@@ -135,7 +140,7 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
             per_launch = ms / n
             flops = layer_flops(L, H, W, N, M) * batch      # a launch covers one task of `batch` frames
             layers[L] = {"avg_us": 1e3 * per_launch, "launches": n, "tflops": flops / (per_launch * 1e-3) / 1e12,
-                         "flops_per_launch": flops}
+                         "flops_per_launch": flops, "form": codec.layer_kernel(L, H, W)[0]}
     mse = torch.mean((out[:steps] - frames[:steps]) ** 2, dim=(1, 2, 3))
     res = {
         "fps": steps / dt,
@@ -403,11 +408,13 @@ def main():
 
     per_layer = main_res["layers"]
     dom = max(per_layer, key=lambda L: per_layer[L]["avg_us"] * per_layer[L]["launches"])
-    peak = PEAK_TFLOPS[dtype]
+    form = per_layer[dom]["form"]
+    peak = round(PEAK_TFLOPS[form], 2)
     ach = per_layer[dom]["tflops"]
     roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4), "traffic": traffic_for(dom) if not prec else None,
-                "kernel": dom, "avg_us": round(per_layer[dom]["avg_us"], 2),
+                "kernel": dom, "form": form, "peak_basis": PEAK_BASIS[form],
+                "avg_us": round(per_layer[dom]["avg_us"], 2),
                 "flops_per_launch": per_layer[dom]["flops_per_launch"]}
 
     res = {
@@ -433,7 +440,8 @@ def main():
         "bpp": round(main_res["bpp"], 4),
         "gpu_busy_s": main_res["gpu_busy_s"],
         "cpu_busy_s": main_res["cpu_busy_s"],
-        "layers": {L: {"avg_us": round(v["avg_us"], 2), "tflops": round(v["tflops"], 2)} for L, v in per_layer.items()},
+        "layers": {L: {"avg_us": round(v["avg_us"], 2), "tflops": round(v["tflops"], 2), "form": v["form"]}
+                   for L, v in per_layer.items()},
         "roofline": roofline,
         "variants": None,
         "cpu_baseline": None,

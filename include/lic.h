@@ -216,6 +216,17 @@ int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
  * it runs on; the accumulators are reset.  codec_layer_time returns the
  * summed kernel time (ms) and launch count of one layer since then. */
 int codec_time_layers(codec_t* c, uint32_t mask);
+
+/* Which kernel a layer launches for one H x W frame (nothing is launched):
+ * *form = the operand form of its GEMM (LIC_FORM_*), *ksplit = the number of
+ * waves that split its K loop (1: one wave per pixel tile).  The choice
+ * depends on the codec's precision and the frame size only. */
+enum { LIC_FORM_F32 = 0,     /* FP32 operands on the FP32 matrix cores */
+       LIC_FORM_BF16 = 1,    /* bf16 operands */
+       LIC_FORM_FP8 = 2,     /* OCP e4m3 operands, per-row weight scales */
+       LIC_FORM_F32X = 3 };  /* FP32 operands as three exact bf16 parts: six
+                                bf16 products per FP32 product, FP32 sums */
+int codec_layer_kernel(codec_t* c, int layer, int H, int W, int* form, int* ksplit);
 int codec_layer_time(codec_t* c, int layer, double* total_ms, long* launches);
 
 /* Entropy tables the codec built at create (host copies, for checking):

@@ -189,6 +189,16 @@ class Codec:
             mask |= 1 << (_lib.LAYER_ID[L] if isinstance(L, str) else int(L))
         self._check(lib.codec_time_layers(self._h, mask))
 
+    FORMS = {0: "f32", 1: "bf16", 2: "fp8", 3: "f32x"}
+
+    def layer_kernel(self, layer, H, W):
+        """(operand form name, K-split waves) of the kernel a layer launches
+        for one H x W frame."""
+        lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
+        form, ks = ctypes.c_int(), ctypes.c_int()
+        self._check(lib.codec_layer_kernel(self._h, lid, H, W, ctypes.byref(form), ctypes.byref(ks)))
+        return self.FORMS[form.value], ks.value
+
     def layer_time(self, layer):
         """(summed kernel milliseconds, launches) of a timed layer."""
         lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)

@@ -292,6 +292,21 @@ int codec_run_layer(codec_t* c, int layer, int n, int H, int W, const void* in, 
     return LIC_OK;
 }
 
+int codec_layer_kernel(codec_t* c, int layer, int H, int W, int* form, int* ksplit)
+{
+    if (!c || !form || !ksplit) return LIC_E_ARG;
+    if (layer < 0 || layer >= LIC_NUM_LAYERS || !c->layers[layer].present) return fail(c, LIC_E_ARG, "no such layer");
+    if (H < 1 || W < 1 || H > 65535 || W > 65535) return fail(c, LIC_E_ARG, "bad size");
+    lic::FrameDims d(H, W);
+    lic::KernelKey key{};
+    std::string e;
+    const int rc = c->launch_layer(layer, 1, d, nullptr, nullptr, nullptr, nullptr, &e, &key);
+    if (rc != LIC_OK) return fail(c, rc, e);
+    *form = key.dt;
+    *ksplit = key.ksplit;
+    return LIC_OK;
+}
+
 int codec_time_layers(codec_t* c, uint32_t mask)
 {
     if (!c) return LIC_E_ARG;

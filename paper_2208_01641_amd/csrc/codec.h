@@ -33,10 +33,11 @@ struct LayerGPU {
     int nphase = 1;
     std::vector<PhaseDesc> host_ph;
     PhaseDesc* d_ph = nullptr;
-    uint8_t* d_w = nullptr;            // packed weights (float or bf16)
+    uint8_t* d_w = nullptr;            // packed weights (float, bf16 or e4m3)
+    uint16_t* d_wx = nullptr;          // FP32 GDN layers: the same as three bf16 parts (ConvArgs::wx)
     float* d_bias = nullptr;
     float* d_rscale = nullptr;         // e4m3 form: per packed row, weight scale x input scale
-    uint16_t* d_gsplit = nullptr;   // gamma as bf16 parts (layout in ConvArgs::gsplit)
+    uint16_t* d_gsplit = nullptr;      // gamma as bf16 parts (layout in ConvArgs::gsplit)
     float* d_beta = nullptr;
     const float* d_qmu = nullptr;      // EP_QUANT offsets
     const float* d_mu_in = nullptr;    // LD_I8 offsets
@@ -325,7 +326,7 @@ struct Codec {
     int build_layers(const std::map<std::string, std::pair<std::vector<int>, std::vector<double>>>& P);
     Geo geo(int layer, const FrameDims& d) const;
     int launch_layer(int layer, int n, const FrameDims& d, const void* in, void* out, void* aux,
-                     hipStream_t s, std::string* errp);
+                     hipStream_t s, std::string* errp, KernelKey* chosen = nullptr);
     // pools and threads
     int start();
     void stop();

@@ -31,6 +31,9 @@ enum DType : int {
     DT_F32 = 0,
     DT_BF16 = 1,
     DT_FP8 = 2,      // OCP e4m3 operands with per-row FP32 scales (rscale)
+    DT_F32X = 3,     // FP32 operands as exact sums of three bf16 parts: the six part
+                     // products of order <= 2 on the bf16 matrix cores, FP32
+                     // accumulation (weights pre-split in ConvArgs::w; FP32 activations)
 };
 
 // One phase of a layer.  A plain convolution has one phase; a stride-2
@@ -51,6 +54,8 @@ struct ConvArgs {
     void* aux;
     const PhaseDesc* ph;     // [nphase] (device)
     const void* w;           // packed weights of every phase (float, bf16 or e4m3)
+    const void* wx;          // the same as bf16 parts for DT_F32X (or null): per 8 channels
+                             // [part 0 x8][part 1 x8][part 2 x8], offsets 3 x those of w
     const void* zero;        // >= 64 zero bytes: the source of out-of-image reads
     const float* bias;       // [CoP]
     const float* mu_in;      // LD_I8 offsets [CIN]

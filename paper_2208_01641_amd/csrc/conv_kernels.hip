@@ -48,15 +48,47 @@ __device__ __forceinline__ f4 mfma16x16x4(float a, float b, f4 c)
 //            lane (one 16-byte load); activations between layers are stored
 //            as bf16, GDN / IGDN and all epilogue arithmetic stay FP32.
 template <int DT> struct Prec;
+// Frag: weight (A) fragment of one lane and K chunk; BIn: pixel (B) values
+// as loaded from NHWC activations; BFrag: B as fed to the matrix cores;
+// Elem / WElem: activation / weight element; WMUL: weight elements per
+// weight value.
 template <> struct Prec<DT_F32> {
     using Frag = f4;
     using Elem = float;
-    static constexpr int KCH = 16, KE = 4;
+    using WElem = float;
+    using BIn = f4;
+    using BFrag = f4;
+    static constexpr int KCH = 16, KE = 4, WMUL = 1;
 };
 template <> struct Prec<DT_BF16> {
     using Frag = bf16x8;
     using Elem = __bf16;
-    static constexpr int KCH = 32, KE = 8;
+    using WElem = __bf16;
+    using BIn = bf16x8;
+    using BFrag = bf16x8;
+    static constexpr int KCH = 32, KE = 8, WMUL = 1;
+};
+//   DT_F32X: FP32 operands split exactly into three bf16 parts (each rounded
+//            to nearest from what the previous parts leave: v = v0 + v1 + v2
+//            up to 2^-27 |v|); the products of parts i + j <= 2 run on
+//            v_mfma_f32_16x16x32_bf16 (each exact in FP32) with FP32
+//            accumulation, so a product carries a relative error near
+//            2^-25, the level of FP32 rounding.  Weights are split on the host
+//            ([part][8] per 8 channels), activations stay FP32 and are split
+//            when a chunk is used.
+struct Split3 {
+    bf16x8 p[3];
+};
+struct F32x8 {
+    f4 lo, hi;
+};
+template <> struct Prec<DT_F32X> {
+    using Frag = Split3;
+    using Elem = float;
+    using WElem = __bf16;
+    using BIn = F32x8;
+    using BFrag = Split3;
+    static constexpr int KCH = 32, KE = 8, WMUL = 3;
 };
 //   DT_FP8 : v_mfma_scale_f32_16x16x128_f8f6f4 on OCP e4m3 operands (unit
 //            block scales), K walked over the flattened (tap, channel) axis in
@@ -67,8 +99,33 @@ template <> struct Prec<DT_BF16> {
 template <> struct Prec<DT_FP8> {
     using Frag = i32x8;
     using Elem = uint8_t;
-    static constexpr int KCH = 128, KE = 32;
+    using WElem = uint8_t;
+    using BIn = i32x8;
+    using BFrag = i32x8;
+    static constexpr int KCH = 128, KE = 32, WMUL = 1;
 };
+
+// eight FP32 values as three bf16 parts (rounded to nearest, remainders exact)
+__device__ __forceinline__ Split3 split3(const float (&v)[8])
+{
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    u32x4 w[3];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+        f2 r = {v[2 * j], v[2 * j + 1]};
+#pragma unroll
+        for (int g = 0; g < 3; ++g) {
+            const b2 h = __builtin_convertvector(r, b2);
+            w[g][j] = __builtin_bit_cast(uint32_t, h);
+            if (g < 2) r -= __builtin_convertvector(h, f2);
+        }
+    }
+    Split3 s;
+#pragma unroll
+    for (int g = 0; g < 3; ++g) s.p[g] = __builtin_bit_cast(bf16x8, w[g]);
+    return s;
+}
 
 // e4m3 code of two floats in the low 16 bits, saturated to +-448 first
 __device__ __forceinline__ uint32_t e4m3x2(float lo, float hi)
@@ -99,11 +156,14 @@ __device__ __forceinline__ int xcd_logical_tile(int L, int T)
 // LDS in the fixed wave order 0, 1, ..., KSPLIT-1, so results do not depend
 // on timing, batch size or which stream runs the kernel.
 template <int TAG, int CIN, int MT, int NT, int WAVES, int KSPLIT, int LD, int EP, int DT>
-__global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
+__global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(ConvArgs a)
 {
     using Frag = typename Prec<DT>::Frag;
     using Elem = typename Prec<DT>::Elem;
-    constexpr int KCH = Prec<DT>::KCH, KE = Prec<DT>::KE;
+    using WElem = typename Prec<DT>::WElem;
+    using BIn = typename Prec<DT>::BIn;
+    using BFrag = typename Prec<DT>::BFrag;
+    constexpr int KCH = Prec<DT>::KCH, KE = Prec<DT>::KE, WMUL = Prec<DT>::WMUL;
     // int8 symbols stay raw in the prefetch ring (with their offsets) and are
     // converted when the chunk is used, so the conversion never waits on a
     // load that is still in flight
@@ -117,10 +177,10 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     };
     using BRaw = typename std::conditional<
         LD == LD_I8 && DT != DT_FP8, I8Raw,
-        typename std::conditional<LD == LD_RGB && DT == DT_BF16, RgbRaw, Frag>::type>::type;
+        typename std::conditional<LD == LD_RGB && (DT == DT_BF16 || DT == DT_F32X), RgbRaw, BIn>::type>::type;
     constexpr int KC = DT == DT_FP8 ? 1 : CIN / KCH;
     static_assert(DT == DT_FP8 ? CIN % 32 == 0 : CIN % KCH == 0, "whole K chunks");
-    static_assert(DT == DT_F32 || LD != LD_F32_ABS, "|y| loader is FP32 only");
+    static_assert(DT == DT_F32 || DT == DT_F32X || LD != LD_F32_ABS, "|y| loader is FP32 only");
     static_assert(KSPLIT == 1 || KSPLIT == WAVES, "split-K blocks share one tile");
     static_assert(KSPLIT == 1 || EP != EP_RGB, "no split-K for the RGB output layer");
     static_assert(EP != EP_MASK || DT == DT_F32, "gradients are FP32");
@@ -141,7 +201,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     // back with readlane / bpermute (no memory access inside the K loop, so
     // the wait for a chunk's operands never covers the prefetched ones)
     const int tapv = lane < ntaps ? (((int)ph->dy[lane] & 0xffff) | ((int)ph->dx[lane] << 16)) : 0;
-    const Elem* __restrict__ wbase = static_cast<const Elem*>(a.w) + ph->woff;
+    const WElem* __restrict__ wbase = static_cast<const WElem*>(a.w) + ph->woff * WMUL;
     const int CoP = a.ncog * MT * 16;
     const int co0 = cog * MT * 16;
 
@@ -154,12 +214,16 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     // (GDN blocks of four unsplit waves keep idle waves: they take part in the
     // barriers of the shared weight and gamma staging)
     constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
-    constexpr bool kALdsEarly = kGLds && DT != DT_FP8 && LD != LD_RGB && MT % 4 == 0;
+    constexpr bool kALdsEarly = kGLds && DT != DT_FP8 && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0;
+    // the split-FP32 form always stages its (three times larger) weight tiles
+    // in LDS: a 2-stage ring filled from one register set
+    constexpr bool kALdsX = DT == DT_F32X;
+    static_assert(!kALdsX || (kGLds && LD != LD_RGB && MT % 4 == 0), "split-FP32 kernels are whole-block GDN layers");
     if (!kGLds && pix0 >= total) return;
     // one LDS buffer for the staged weight ring of the K loop and, after it,
     // the staged gamma slices of the GDN epilogue
-    constexpr int kGP = DT == DT_F32 ? 3 : 2;                   // bf16 parts of gamma
-    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : 0;
+    constexpr int kGP = (DT == DT_F32 || DT == DT_F32X) ? 3 : 2;   // bf16 parts of gamma
+    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : kALdsX ? 2 * MT * 16 * 52 : 0;
     constexpr int kGWords = kGLds ? 2 * kGP * MT * 16 * 16 : 0;
     constexpr int kSmemWords = (kAWords > kGWords ? kAWords : kGWords) > 0 ? (kAWords > kGWords ? kAWords : kGWords) : 4;
     __shared__ __attribute__((aligned(16))) uint32_t smem[kSmemWords];
@@ -187,9 +251,9 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     }
 
     auto loadA = [&](int t, int kc, Frag (&A)[MT]) __attribute__((always_inline)) {
-        const Elem* wp = wbase + ((long)t * CoP + co0 + l16) * CIN + kc * KCH + kg * KE;
+        const WElem* wp = wbase + (((long)t * CoP + co0 + l16) * CIN + kc * KCH + kg * KE) * WMUL;
 #pragma unroll
-        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
+        for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN * WMUL);
     };
 
     auto loadB = [&](int t, int kc, BRaw (&B)[NT]) __attribute__((always_inline)) {
@@ -222,7 +286,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                         }
                     }
                 }
-                if constexpr (DT == DT_BF16) {
+                if constexpr (DT == DT_BF16 || DT == DT_F32X) {
                     RgbRaw r;
 #pragma unroll
                     for (int e = 0; e < KE; ++e) r.x[e] = x[e];
@@ -261,7 +325,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
                     B[nt] = r;
                 } else {
                     const Elem* src = ok ? static_cast<const Elem*>(a.in) + off : static_cast<const Elem*>(a.zero);
-                    B[nt] = *reinterpret_cast<const Frag*>(src);
+                    B[nt] = *reinterpret_cast<const BIn*>(src);
                 }
             }
         }
@@ -269,8 +333,24 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 
     // the B operand of a ring entry: int8 symbols + offsets converted, |y|
     // taken for the h_a input, everything else as loaded
-    auto cook = [&](const BRaw& r) __attribute__((always_inline)) -> Frag {
-        if constexpr (LD == LD_I8 && DT != DT_FP8) {
+    auto cook = [&](const BRaw& r) __attribute__((always_inline)) -> BFrag {
+        if constexpr (DT == DT_F32X) {
+            float v[8];
+            if constexpr (LD == LD_I8) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = (float)(int8_t)(r.w[e / 4] >> (8 * (e % 4))) + r.mu[e];
+            } else if constexpr (LD == LD_RGB) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) v[e] = r.x[e];
+            } else {
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = LD == LD_F32_ABS ? fabsf(r.lo[e]) : r.lo[e];
+                    v[4 + e] = LD == LD_F32_ABS ? fabsf(r.hi[e]) : r.hi[e];
+                }
+            }
+            return split3(v);
+        } else if constexpr (LD == LD_I8 && DT != DT_FP8) {
             Frag v;
 #pragma unroll
             for (int e = 0; e < KE; ++e) v[e] = (Elem)((float)(int8_t)(r.w[e / 4] >> (8 * (e % 4))) + r.mu[e]);
@@ -290,11 +370,25 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         }
     };
 
+    // the six part products of the split-FP32 form, smallest first
+    auto mfma_x = [](const Split3& A, const Split3& B, f4 c) __attribute__((always_inline)) -> f4 {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[0], B.p[2], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[1], B.p[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[2], B.p[0], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[0], B.p[1], c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[1], B.p[0], c, 0, 0, 0);
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.p[0], B.p[0], c, 0, 0, 0);
+    };
     auto compute = [&](const Frag (&A)[MT], const BRaw (&Braw)[NT]) __attribute__((always_inline)) {
-        Frag B[NT];
+        BFrag B[NT];
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) B[nt] = cook(Braw[nt]);
-        if constexpr (DT == DT_F32) {
+        if constexpr (DT == DT_F32X) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_x(A[mt], B[nt], acc[mt][nt]);
+        } else if constexpr (DT == DT_F32) {
 #pragma unroll
             for (int e = 0; e < 4; ++e)
 #pragma unroll
@@ -325,8 +419,8 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
             // past the last tap: read the zero page (no divergent load)
-            const Elem* src = t < ntaps ? wbase + ((long)t * CoP + co0 + mt * 16 + l16) * CIN + c
-                                        : static_cast<const Elem*>(a.zero);
+            const WElem* src = t < ntaps ? wbase + ((long)t * CoP + co0 + mt * 16 + l16) * CIN + c
+                                         : static_cast<const WElem*>(a.zero);
             A[mt] = *reinterpret_cast<const Frag*>(src);
         }
     };
@@ -334,6 +428,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
         return (int)(e4m3x2(v0, v1) | (e4m3x2(v2, v3) << 16));
     };
     auto loadB8 = [&](int kc, Frag (&B)[NT]) __attribute__((always_inline)) {
+      if constexpr (DT == DT_FP8) {
         const int f = kc * KCH + kg * KE;
         const int t = f / CIN, c = f - (f / CIN) * CIN;
 #pragma unroll
@@ -394,11 +489,12 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             }
             B[nt] = v;
         }
+      }
     };
 
     // stores 4 consecutive channels of one pixel in the activation storage type
     auto store_act = [&](long idx, const f4& y) __attribute__((always_inline)) {
-        if constexpr (DT == DT_F32) {
+        if constexpr (DT == DT_F32 || DT == DT_F32X) {
             *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
         } else if constexpr (DT == DT_FP8) {
             const float q = a.out_q;
@@ -419,7 +515,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     constexpr int STAGE = (MT * (int)sizeof(Frag) + NT * (int)sizeof(BRaw)) / 4;   // VGPRs per chunk buffer
     constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
     // (the image loader has only a handful of chunks: keep its ring short)
-    constexpr int P = kALdsEarly ? 3
+    constexpr int P = kALdsX ? 2 : kALdsEarly ? 3
                   : (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
@@ -466,7 +562,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             } else {
                 const Elem* src = pok[nt] ? static_cast<const Elem*>(a.in) + pixoff[nt] + cur_kc * KCH
                                           : static_cast<const Elem*>(a.zero);
-                B[nt] = *reinterpret_cast<const Frag*>(src);
+                B[nt] = *reinterpret_cast<const BIn*>(src);
             }
         }
         cur_t += KSPLIT;
@@ -479,9 +575,9 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
     };
     auto load_cursor = [&](Frag (&A)[MT], BRaw (&B)[NT]) __attribute__((always_inline)) {
         if constexpr (kCursor) {
-            const Elem* wp = wbase + ((long)cur_t * CoP + co0 + l16) * CIN + cur_kc * KCH + kg * KE;
+            const WElem* wp = wbase + (((long)cur_t * CoP + co0 + l16) * CIN + cur_kc * KCH + kg * KE) * WMUL;
 #pragma unroll
-            for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN);
+            for (int mt = 0; mt < MT; ++mt) A[mt] = *reinterpret_cast<const Frag*>(wp + (long)mt * 16 * CIN * WMUL);
             cursor_loadB(B);
         }
     };
@@ -516,7 +612,7 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
 #pragma unroll
             for (int i = 0; i < NPIECE; ++i) {
                 const int q = tid + i * 256, row = q >> 2, c16 = q & 3;
-                const Elem* src = wbase + ((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH + c16 * (16 / (int)sizeof(Elem));
+                const WElem* src = wbase + ((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH + c16 * (16 / (int)sizeof(WElem));
                 r[i] = *reinterpret_cast<const u32x4*>(src);
             }
             if (++a_t == ntaps) {
@@ -578,9 +674,87 @@ __global__ void __launch_bounds__(64 * WAVES) conv_igemm(ConvArgs a)
             if (k0 + 2 < nk) step(k0 + 2, J2{}, true);
         }
     }
-    Frag Ab[kALds ? 1 : P][MT];
-    BRaw Bb[kALds ? 1 : P][NT];
-    if constexpr (!kALds) {
+    if constexpr (kALdsX) {
+        // Split-FP32 weights: per chunk a row holds 32 channels x 3 parts
+        // (192 bytes, twelve 16-byte pieces), padded to 208 bytes in LDS so
+        // that the 16 rows read by one 16-byte load land in distinct banks.
+        // Chunk k + 1 is fetched into registers (issued before the pixel
+        // prefetch, so waiting for it never waits for those) while chunk k
+        // feeds the matrix cores, then stored to the other stage; one barrier
+        // per chunk.
+        constexpr int PPR = 12;
+        constexpr int AROW = 52;
+        constexpr int ROWS = MT * 16;
+        constexpr int NPIECE = ROWS * PPR / 256;
+        static_assert(ROWS * PPR % 256 == 0, "whole pieces per thread");
+        static_assert(2 * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
+        uint32_t* const As = smem;                          // [2][ROWS][AROW]
+        const int tid = threadIdx.x;
+        int a_t = 0, a_kc = 0;
+        u32x4 ra[NPIECE];
+        auto a_gload = [&]() __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < NPIECE; ++i) {
+                const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
+                const WElem* src = wbase + (((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH) * 3 + c * 8;
+                ra[i] = *reinterpret_cast<const u32x4*>(src);
+            }
+            if (++a_t == ntaps) {
+                a_t = 0;
+                ++a_kc;
+            }
+        };
+        auto a_store = [&](int stage) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < NPIECE; ++i) {
+                const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
+                *reinterpret_cast<u32x4*>(&As[(stage * ROWS + row) * AROW + c * 4]) = ra[i];
+            }
+        };
+        BRaw Bb[P][NT];
+        // prologue: chunk 0 in LDS, pixels of chunks 0 .. P - 2 in flight
+        if (0 < nk) a_gload();
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j)
+            if (j < nk) cursor_loadB(Bb[j]);
+        if (0 < nk) a_store(0);
+        __syncthreads();
+        auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;
+            if (!guard || k + 1 < nk) a_gload();
+            if (!guard || k + P - 1 < nk) cursor_loadB(Bb[(j + P - 1) % P]);
+            BFrag B[NT];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) B[nt] = cook(Bb[j][nt]);
+            const int base = (j * ROWS + l16) * AROW + kg * 12;          // stage k % 2 = j
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                Split3 A;
+#pragma unroll
+                for (int g = 0; g < 3; ++g)
+                    A.p[g] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const u32x4*>(&As[base + mt * 16 * AROW + g * 4]));
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_x(A, B[nt], acc[mt][nt]);
+            }
+            if (!guard || k + 1 < nk) a_store(1 - j);
+            __syncthreads();
+        };
+        static_assert(P == 2, "the split-FP32 loop is written for a 2-deep pixel ring");
+        int k0 = 0;
+        using J0 = std::integral_constant<int, 0>;
+        using J1 = std::integral_constant<int, 1>;
+        for (; k0 + 2 < nk; k0 += 2) {
+            step(k0, J0{}, false);
+            step(k0 + 1, J1{}, false);
+        }
+        for (; k0 < nk; k0 += 2) {
+            step(k0, J0{}, true);
+            if (k0 + 1 < nk) step(k0 + 1, J1{}, true);
+        }
+    }
+    Frag Ab[(kALds || kALdsX) ? 1 : P][MT];
+    BRaw Bb[(kALds || kALdsX) ? 1 : P][NT];
+    if constexpr (!kALds && !kALdsX) {
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
         if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
@@ -899,6 +1073,8 @@ struct KernelEntry {
 #define LIC_K2B(TAG, CIN, LD, EP)                                                                \
     LIC_KSD(TAG, CIN, 4, 2, 4, 1, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 4, 2, 4, 4, LD, EP, DT_BF16), \
         LIC_KSD(TAG, CIN, 4, 2, 8, 8, LD, EP, DT_BF16), LIC_KSD(TAG, CIN, 1, 1, 8, 8, LD, EP, DT_BF16)
+// split-FP32 operands: whole-frame GDN layers of the FP32 form
+#define LIC_KX(TAG, CIN, MT, NT, LD, EP) LIC_KSD(TAG, CIN, MT, NT, 4, 1, LD, EP, DT_F32X)
 // e4m3 operand variants (precision form): g_a and g_s
 #define LIC_KF(TAG, CIN, MT, NT, WV, LD, EP) LIC_KSD(TAG, CIN, MT, NT, WV, 1, LD, EP, DT_FP8)
 #define LIC_KGF(TAG, CIN, MT, NT, LD, EP) \
@@ -936,6 +1112,11 @@ static const KernelEntry kEntries[] = {
     LIC_KG(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KG(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_K(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_K(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    LIC_KX(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KX(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_KX(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KX(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
+    LIC_KX(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KX(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
+    LIC_KX(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KX(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     // bf16 operands (precision form): g_a and g_s; h_a / h_s stay FP32
     LIC_KB(LIC_GA0, 96, 8, 2, 4, LD_RGB, EP_GDN), LIC_KB(LIC_GA0, 96, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGB(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGB(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),

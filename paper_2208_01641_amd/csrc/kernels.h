@@ -36,6 +36,8 @@ struct ConvShape {
 // (the pixel grid of one image, so that results do not depend on the batch),
 // sets a.ncog and launches over the a.n x a.Hg x a.Wg grid.  Returns a
 // lic_status; *errp names the failure.
-int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp);
+// With chosen non-null nothing is launched: the configuration is stored there.
+int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp,
+                       KernelKey* chosen = nullptr);
 
 }  // namespace lic

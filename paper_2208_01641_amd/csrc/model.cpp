@@ -366,6 +366,27 @@ int Codec::build_layers(const ParamMap& P)
             HIP_TRY(hipMemcpy(L.d_w, h8.data(), total, hipMemcpyHostToDevice));
         } else {
             HIP_TRY(hipMemcpy(L.d_w, wp.data(), total * esz, hipMemcpyHostToDevice));
+            if (sp.ep == EP_GDN || sp.ep == EP_IGDN) {
+                // split-FP32 operands of the whole-frame kernels: each group of
+                // 8 packed values as [part 0 x8][part 1 x8][part 2 x8], the
+                // parts rounded to nearest from what the previous ones leave
+                if (total % 8 != 0) { err = std::string("packing mismatch in ") + sp.name; return LIC_E_MODEL; }
+                std::vector<uint16_t> hx(3 * total);
+                for (size_t j = 0; j < total; ++j) {
+                    float rem = wp[j];
+                    for (int g = 0; g < 3; ++g) {
+                        const uint16_t h = bf16_rne(rem);
+                        hx[24 * (j / 8) + 8 * g + j % 8] = h;
+                        const uint32_t u = (uint32_t)h << 16;
+                        float hv;
+                        memcpy(&hv, &u, 4);
+                        rem -= hv;
+                    }
+                }
+                L.d_wx = (uint16_t*)dev_alloc(hx.size() * sizeof(uint16_t));
+                if (!L.d_wx) { err = "device allocation failed"; return LIC_E_NOMEM; }
+                HIP_TRY(hipMemcpy(L.d_wx, hx.data(), hx.size() * sizeof(uint16_t), hipMemcpyHostToDevice));
+            }
         }
         for (size_t i = 0; i < ph.size(); ++i) ph[i].woff = (int64_t)pm.off[i];
         HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
@@ -425,7 +446,7 @@ Geo Codec::geo(int id, const FrameDims& d) const
 }
 
 int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void* out, void* aux, hipStream_t s,
-                        std::string* errp)
+                        std::string* errp, KernelKey* chosen)
 {
     if (id < 0 || id >= LIC_NUM_LAYERS || !layers[id].present) { *errp = "layer not present in this model"; return LIC_E_ARG; }
     const LayerGPU& L = layers[id];
@@ -436,6 +457,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.aux = aux;
     a.ph = L.d_ph;
     a.w = L.d_w;
+    a.wx = L.d_wx;
     a.zero = d_zero;
     a.bias = L.d_bias;
     a.mu_in = L.d_mu_in;
@@ -463,10 +485,11 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.out_q = kActQ;
 
     const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase};
-    return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp);
+    return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp, chosen);
 }
 
-int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp)
+int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipStream_t s, std::string* errp,
+                       KernelKey* chosen)
 {
     KernelKey key{L.tag, L.cin, 0, 0, 0, 1, L.ld, L.ep, L.dt};
     const long pixels = (long)a.n * a.Hg * a.Wg;
@@ -504,12 +527,25 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
         }
         a.ncog = L.cop / (16 * key.mt);
     }
+    // whole-frame GDN layers of the FP32 form run on split-FP32 operands
+    if (key.dt == DT_F32 && key.ksplit == 1 && a.wx && (L.ep == EP_GDN || L.ep == EP_IGDN)) {
+        KernelKey kx = key;
+        kx.dt = DT_F32X;
+        if (kernel_available(kx)) {
+            key = kx;
+            a.w = a.wx;
+        }
+    }
     const long per_block = (long)(key.waves / key.ksplit) * key.nt * 16;
     const long tiles = (pixels + per_block - 1) / per_block;
     const long nblocks = tiles * L.nphase * a.ncog;
-    if (nblocks <= 0) return LIC_OK;
+    if (nblocks <= 0 && !chosen) return LIC_OK;
     if (nblocks > (1L << 30)) { *errp = "launch too large"; return LIC_E_BUDGET; }
     if (!kernel_available(key)) { *errp = "no kernel instantiated for this layer shape"; return LIC_E_ARG; }
+    if (chosen) {
+        *chosen = key;
+        return LIC_OK;
+    }
     hipError_t e = launch_conv(key, a, (int)nblocks, s);
     if (e != hipSuccess) {
         *errp = std::string("kernel launch failed: ") + hipGetErrorString(e);

@@ -183,3 +183,19 @@ def test_batched_layers_equal_single(torch_dev):
             if ab is not None:
                 assert torch.equal(a1[0], ab[i])
     c.close()
+
+
+def test_layer_kernel_forms(torch_dev):
+    """The kernel choice follows the precision and the frame size: whole
+    frames run the GDN layers of the FP32 form on split-FP32 operands, small
+    frames split K over the waves of a block (FP32 matrix cores)."""
+    c, _ = make_codec(1, 128, 192, max_h=720, max_w=1280, max_in_flight=1)
+    assert c.layer_kernel("GA1", 720, 1280) == ("f32x", 1)
+    assert c.layer_kernel("GS2", 720, 1280) == ("f32x", 1)
+    assert c.layer_kernel("GA1", 128, 128) == ("f32", 4)
+    assert c.layer_kernel("HS2", 720, 1280)[0] == "f32"
+    c.close()
+    c, _ = make_codec(1, 128, 192, precision=1, max_h=720, max_w=1280, max_in_flight=1)
+    assert c.layer_kernel("GA1", 720, 1280) == ("bf16", 1)
+    assert c.layer_kernel("HA1", 720, 1280)[0] == "f32"       # the hyper path stays FP32
+    c.close()
