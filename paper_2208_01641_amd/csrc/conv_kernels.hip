@@ -1117,6 +1117,10 @@ static const KernelEntry kEntries[] = {
     LIC_KX(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KX(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
     LIC_KX(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KX(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
+    // (one pixel group per wave: grids between half and one wave per SIMD)
+    LIC_KX(LIC_GA1, 128, 8, 1, LD_F32, EP_GDN), LIC_KX(LIC_GA2, 128, 8, 1, LD_F32, EP_GDN),
+    LIC_KX(LIC_GS0, 192, 8, 1, LD_I8, EP_IGDN), LIC_KX(LIC_GS1, 128, 8, 1, LD_F32, EP_IGDN),
+    LIC_KX(LIC_GS2, 128, 8, 1, LD_F32, EP_IGDN),
     // bf16 operands (precision form): g_a and g_s; h_a / h_s stay FP32
     LIC_KB(LIC_GA0, 96, 8, 2, 4, LD_RGB, EP_GDN), LIC_KB(LIC_GA0, 96, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGB(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGB(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
@@ -1126,6 +1130,9 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    LIC_KB(LIC_GA1, 128, 8, 1, 4, LD_F32, EP_GDN), LIC_KB(LIC_GA2, 128, 8, 1, 4, LD_F32, EP_GDN),
+    LIC_KB(LIC_GS0, 192, 8, 1, 4, LD_I8, EP_IGDN), LIC_KB(LIC_GS1, 128, 8, 1, 4, LD_F32, EP_IGDN),
+    LIC_KB(LIC_GS2, 128, 8, 1, 4, LD_F32, EP_IGDN),
     // e4m3 operands (precision form): g_a and g_s
     LIC_KF(LIC_GA0, 128, 8, 2, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),

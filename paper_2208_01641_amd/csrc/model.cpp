@@ -501,7 +501,16 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
         // fewer than one wave per SIMD (1024 on the chip) from the pixel
         // grid of one image: split K over the 4 waves of a block instead
         const long img_waves = (policy_pixels + 16 * key.nt - 1) / (16 * key.nt) * L.nphase;
-        if (L.ld != LD_RGB && img_waves < 1024) key.ksplit = 4;
+        if (L.ld != LD_RGB && img_waves < 1024) {
+            // one 16-pixel group per wave first, if that gives at least half
+            // a wave per SIMD (and such a kernel exists); else split K
+            const long waves1 = (policy_pixels + 15) / 16 * L.nphase;
+            KernelKey k1 = key;
+            k1.nt = 1;
+            if (k1.dt == DT_F32 && a.wx) k1.dt = DT_F32X;
+            if (key.nt == 2 && waves1 >= 512 && kernel_available(k1)) key.nt = 1;
+            else key.ksplit = 4;
+        }
     } else if (L.ep == EP_RGB) {
         // every row of the transposed convolution to 3 channels in one wave
         key.mt = L.cop / 16;

@@ -192,6 +192,8 @@ def test_layer_kernel_forms(torch_dev):
     c, _ = make_codec(1, 128, 192, max_h=720, max_w=1280, max_in_flight=1)
     assert c.layer_kernel("GA1", 720, 1280) == ("f32x", 1)
     assert c.layer_kernel("GS2", 720, 1280) == ("f32x", 1)
+    assert c.layer_kernel("GA2", 720, 1280) == ("f32x", 1)     # one pixel group per wave
+    assert c.layer_kernel("GS0", 720, 1280) == ("f32x", 1)
     assert c.layer_kernel("GA1", 128, 128) == ("f32", 4)
     assert c.layer_kernel("HS2", 720, 1280)[0] == "f32"
     c.close()
