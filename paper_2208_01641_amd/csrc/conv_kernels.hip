@@ -215,10 +215,10 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // barriers of the shared weight and gamma staging)
     constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
     constexpr bool kALdsEarly = kGLds && DT != DT_FP8 && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0;
-    // the split-FP32 form always stages its (three times larger) weight tiles
-    // in LDS: a 2-stage ring filled from one register set
-    constexpr bool kALdsX = DT == DT_F32X;
-    static_assert(!kALdsX || (kGLds && LD != LD_RGB && MT % 4 == 0), "split-FP32 kernels are whole-block GDN layers");
+    // the split-FP32 form stages the (three times larger) weight tiles of its
+    // GDN layers in LDS: a 2-stage ring filled from one register set (other
+    // shapes would load them per wave)
+    constexpr bool kALdsX = DT == DT_F32X && kGLds && MT % 4 == 0;
     if (!kGLds && pix0 >= total) return;
     // one LDS buffer for the staged weight ring of the K loop and, after it,
     // the staged gamma slices of the GDN epilogue
@@ -515,7 +515,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     constexpr int STAGE = (MT * (int)sizeof(Frag) + NT * (int)sizeof(BRaw)) / 4;   // VGPRs per chunk buffer
     constexpr int BUDGET = WAVES >= 8 ? 64 : 128;                     // VGPRs for the ring
     // (the image loader has only a handful of chunks: keep its ring short)
-    constexpr int P = kALdsX ? 2 : kALdsEarly ? 3
+    constexpr int P = DT == DT_F32X ? 2 : kALdsEarly ? 3
                   : (LD == LD_RGB || BUDGET / STAGE < 2) ? 2 : (BUDGET / STAGE > 4 ? 4 : BUDGET / STAGE);
     const int K = DT == DT_FP8 ? (ntaps * CIN + KCH - 1) / KCH : ntaps * KC;
     const int nk = (K - kslot + KSPLIT - 1) / KSPLIT;
@@ -712,17 +712,23 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             }
         };
         BRaw Bb[P][NT];
+        // pixels of chunk kk: the gathered loaders walk their cursor, the
+        // image loader takes the flat chunk index
+        auto loadBk = [&](int kk, BRaw (&B)[NT]) __attribute__((always_inline)) {
+            if constexpr (kCursor) cursor_loadB(B);
+            else loadB(kk / KC, kk % KC, B);
+        };
         // prologue: chunk 0 in LDS, pixels of chunks 0 .. P - 2 in flight
         if (0 < nk) a_gload();
 #pragma unroll
         for (int j = 0; j < P - 1; ++j)
-            if (j < nk) cursor_loadB(Bb[j]);
+            if (j < nk) loadBk(j, Bb[j]);
         if (0 < nk) a_store(0);
         __syncthreads();
         auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
             if (!guard || k + 1 < nk) a_gload();
-            if (!guard || k + P - 1 < nk) cursor_loadB(Bb[(j + P - 1) % P]);
+            if (!guard || k + P - 1 < nk) loadBk(k + P - 1, Bb[(j + P - 1) % P]);
             BFrag B[NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) B[nt] = cook(Bb[j][nt]);
@@ -818,6 +824,38 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         ox[nt] = gx[nt] * a.s_out + ph->ox;
         obase[nt] = (((long)img[nt] * a.Hout + oy[nt]) * a.Wout + ox[nt]) * a.Co;
     }
+
+    // Byte outputs (symbols, scale indices) often go straight to mapped host
+    // memory: stage the wave's tile in LDS and write each pixel's MT x 16
+    // channel bytes as whole 16-byte pieces (one 64-byte line for MT = 4)
+    // rather than 4-byte pieces spread over the lanes.
+    constexpr bool kBytes = EP == EP_QUANT || EP == EP_INDEX;
+    __shared__ __attribute__((aligned(16))) uint32_t obytes[kBytes ? PIXW : 1][kBytes ? NT * 16 : 1][kBytes ? MT * 4 : 1];
+    auto store_bytes = [&](const uint32_t (&pk)[MT][NT], uint8_t* dst) __attribute__((always_inline)) {
+        uint32_t (&w)[kBytes ? NT * 16 : 1][kBytes ? MT * 4 : 1] = obytes[wave / KSPLIT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) w[nt * 16 + l16][mt * 4 + kg] = pk[mt][nt];
+        // lanes of one wave read each other's words: LDS completes a wave's
+        // accesses in order; the fences keep the compiler from reordering
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        constexpr int PIECES = NT * 16 * MT;                 // 16-byte pieces of the tile
+#pragma unroll
+        for (int q0 = 0; q0 < PIECES; q0 += 64) {
+            const int q = q0 + lane;
+            const int p = q / MT, m = q - (q / MT) * MT;
+            const int P = pix0 + p;
+            if ((PIECES % 64 == 0 || q < PIECES) && P < total && co0 + m * 16 < a.Co) {
+                const int im = P / HWg, r = P - (P / HWg) * HWg;
+                const int yy = r / a.Wg, xx = r - (r / a.Wg) * a.Wg;
+                const long o = (((long)im * a.Hout + yy * a.s_out + ph->oy) * a.Wout + xx * a.s_out + ph->ox) * a.Co;
+                *reinterpret_cast<u32x4*>(dst + o + co0 + m * 16) = *reinterpret_cast<const u32x4*>(&w[p][m * 4]);
+            }
+        }
+    };
 
     if constexpr (EP == EP_GDN || EP == EP_IGDN) {
         // n = beta + gamma (x*x): [Co x Co] x [Co x pixels] on the bf16 matrix
@@ -964,15 +1002,15 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             }
     } else if constexpr (EP == EP_QUANT) {
         float* out = static_cast<float*>(a.out);
-        int8_t* sym = static_cast<int8_t*>(a.aux);
+        uint32_t pk[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int c = co0 + mt * 16 + kg * 4;
-                if (!(pv[nt] && c < a.Co)) continue;
+                const bool ok = pv[nt] && c < a.Co;
                 const f4 y = acc[mt][nt];
-                const f4 mu = *reinterpret_cast<const f4*>(a.qmu + c);
+                const f4 mu = ok ? *reinterpret_cast<const f4*>(a.qmu + c) : f4{0.0f, 0.0f, 0.0f, 0.0f};
                 uint32_t packed = 0;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
@@ -980,39 +1018,60 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
                     q = fminf(fmaxf(q, -64.0f), 64.0f);
                     packed |= ((uint32_t)((int)q) & 0xffu) << (8 * i);
                 }
-                if (out) *reinterpret_cast<f4*>(out + obase[nt] + c) = y;
-                *reinterpret_cast<uint32_t*>(sym + obase[nt] + c) = packed;
+                pk[mt][nt] = packed;
+                if (out && ok) *reinterpret_cast<f4*>(out + obase[nt] + c) = y;
             }
+        store_bytes(pk, static_cast<uint8_t*>(a.aux));
     } else if constexpr (EP == EP_INDEX) {
         uint8_t* idxo = static_cast<uint8_t*>(a.out);
         float* vout = static_cast<float*>(a.aux);
         const float* __restrict__ thr = a.thr;
+        // idx = #{k < 63 : thr[k] < s} with s = v (thr holds ln t_k: exp(v) >
+        // t_k <=> v > ln t_k) or s = max(v, 0, t_0) (thr holds t_k).  The
+        // thresholds are the same for every lane: they are read as scalars, 16
+        // at a time, and counted against every element of the tile (a
+        // per-lane search would gather them).
+        float sv[MT][NT][4];
+        int cnt[MT][NT][4];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float y = acc[mt][nt][i];
+                    sv[mt][nt][i] = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), thr[0]);
+                    cnt[mt][nt][i] = 0;
+                }
+#pragma unroll 1
+        for (int k0 = 0; k0 < 64; k0 += 16) {
+            float t[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) t[j] = thr[k0 + j < 63 ? k0 + j : 62];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+                const bool real = k0 + j < 63;              // 63 thresholds
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+                    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) cnt[mt][nt][i] += (real && t[j] < sv[mt][nt][i]) ? 1 : 0;
+            }
+        }
+        uint32_t pk[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int c = co0 + mt * 16 + kg * 4;
-                if (!(pv[nt] && c < a.Co)) continue;
-                const f4 y = acc[mt][nt];
                 uint32_t packed = 0;
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    // exp output: exp(v) > t_k  <=>  v > ln t_k (thr holds ln t_k);
-                    // ReLU output: max(v, 0, t_0) against t_k (thr holds t_k).
-                    const float s = a.hs_exp ? y[i] : fmaxf(fmaxf(y[i], 0.0f), thr[0]);
-                    int lo = 0, hi = 63;            // idx = #{k < 63 : thr[k] < s}
-#pragma unroll
-                    for (int it = 0; it < 6; ++it) {
-                        const int mid = (lo + hi) >> 1;
-                        if (lo < hi) {
-                            if (thr[mid] < s) lo = mid + 1; else hi = mid;
-                        }
-                    }
-                    packed |= (uint32_t)lo << (8 * i);
-                }
-                *reinterpret_cast<uint32_t*>(idxo + obase[nt] + c) = packed;
-                if (vout) *reinterpret_cast<f4*>(vout + obase[nt] + c) = y;
+                for (int i = 0; i < 4; ++i) packed |= (uint32_t)cnt[mt][nt][i] << (8 * i);
+                pk[mt][nt] = packed;
+                if (vout && pv[nt] && c < a.Co) *reinterpret_cast<f4*>(vout + obase[nt] + c) = acc[mt][nt];
             }
+        store_bytes(pk, idxo);
     } else if constexpr (EP == EP_RGB) {
         // rows r = 3 (S py + px) + c are the S x S sub-pixel phases of the 3
         // output channels of a stride-S transposed convolution (S = s_out)
@@ -1095,7 +1154,7 @@ struct KernelEntry {
 static const KernelEntry kEntries[] = {
     // g_a: GDN layers hold every channel of their pixels in one wave (split-K
     // variants for grids that would leave SIMDs idle)
-    LIC_K(LIC_GA0, 80, 8, 2, 4, LD_RGB, EP_GDN), LIC_K(LIC_GA0, 80, 12, 1, 4, LD_RGB, EP_GDN),
+    LIC_K(LIC_GA0, 96, 8, 2, 4, LD_RGB, EP_GDN), LIC_K(LIC_GA0, 96, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KG(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KG(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KG(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KG(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_K2(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2(LIC_GA3, 192, LD_F32, EP_QUANT),
@@ -1117,6 +1176,7 @@ static const KernelEntry kEntries[] = {
     LIC_KX(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KX(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
     LIC_KX(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KX(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
+    LIC_KX(LIC_GA0, 96, 8, 2, LD_RGB, EP_GDN), LIC_KX(LIC_GA0, 96, 12, 1, LD_RGB, EP_GDN),
     // (one pixel group per wave: grids between half and one wave per SIMD)
     LIC_KX(LIC_GA1, 128, 8, 1, LD_F32, EP_GDN), LIC_KX(LIC_GA2, 128, 8, 1, LD_F32, EP_GDN),
     LIC_KX(LIC_GS0, 192, 8, 1, LD_I8, EP_IGDN), LIC_KX(LIC_GS1, 128, 8, 1, LD_F32, EP_IGDN),

@@ -308,7 +308,7 @@ int Codec::build_layers(const ParamMap& P)
         const bool is_gags = sp.id <= LIC_GA3 || sp.id >= LIC_GS0;
         L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
         // 75 (tap, channel) pairs in whole K chunks
-        const int krgb = L.dt == DT_BF16 ? 96 : L.dt == DT_FP8 ? 128 : 80;
+        const int krgb = L.dt == DT_FP8 ? 128 : 96;
         L.cin = sp.ld == LD_RGB ? krgb : ci;
         L.cop = L.rows ? 16 : co;
         if (sp.ld == LD_RGB && ci != 3) { err = "ga0 must take 3 channels"; return LIC_E_MODEL; }

@@ -194,6 +194,8 @@ def test_layer_kernel_forms(torch_dev):
     assert c.layer_kernel("GS2", 720, 1280) == ("f32x", 1)
     assert c.layer_kernel("GA2", 720, 1280) == ("f32x", 1)     # one pixel group per wave
     assert c.layer_kernel("GS0", 720, 1280) == ("f32x", 1)
+    assert c.layer_kernel("GA0", 720, 1280) == ("f32x", 1)     # image loader
+    assert c.layer_kernel("GS3", 720, 1280) == ("f32", 1)      # output layer: FP32 matrix cores
     assert c.layer_kernel("GA1", 128, 128) == ("f32", 4)
     assert c.layer_kernel("HS2", 720, 1280)[0] == "f32"
     c.close()
