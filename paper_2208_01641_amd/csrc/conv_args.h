@@ -11,6 +11,10 @@ enum Loader : int {
     LD_I8 = 2,       // int8 NHWC symbols, dequantised as sym + mu[c]
     LD_RGB = 3,      // float NCHW 3-channel tensor, kk x kk taps flattened with the
                      // channels (image ingest with its zero pad; 3-channel gradients)
+    LD_TILE = 4,     // float / bf16 NHWC activations of a stride-1 grid whose taps lie
+                     // within one pixel: each block stages its tile of rows (one per
+                     // wave) with a one-pixel halo, and the weights, in LDS per
+                     // channel slice
 };
 
 // Epilogues fused after the K loop.

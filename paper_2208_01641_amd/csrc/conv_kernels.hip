@@ -219,26 +219,49 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // GDN layers in LDS: a 2-stage ring filled from one register set (other
     // shapes would load them per wave)
     constexpr bool kALdsX = DT == DT_F32X && kGLds && MT % 4 == 0;
-    if (!kGLds && pix0 >= total) return;
+    if (!kGLds && LD != LD_TILE && pix0 >= total) return;
     // one LDS buffer for the staged weight ring of the K loop and, after it,
     // the staged gamma slices of the GDN epilogue
     constexpr int kGP = (DT == DT_F32 || DT == DT_F32X) ? 3 : 2;   // bf16 parts of gamma
-    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : kALdsX ? 2 * MT * 16 * 52 : 0;
+    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : kALdsX ? 2 * MT * 16 * 52
+                          : LD == LD_TILE ? 2 * ((WAVES + 2) * (NT * 16 + 2) + 9 * MT * 16) * 16 : 0;
     constexpr int kGWords = kGLds ? 2 * kGP * MT * 16 * 16 : 0;
     constexpr int kSmemWords = (kAWords > kGWords ? kAWords : kGWords) > 0 ? (kAWords > kGWords ? kAWords : kGWords) : 4;
     __shared__ __attribute__((aligned(16))) uint32_t smem[kSmemWords];
 
     int img[NT], gy[NT], gx[NT];
     bool pv[NT];
+    // halo-tile loader: the block covers TH grid rows (one per wave) of TW
+    // pixels starting at (t_y0, t_x0) of image t_img
+    constexpr bool kTile = LD == LD_TILE;
+    static_assert(!kTile || (KSPLIT == 1 && (DT == DT_F32 || DT == DT_BF16)), "halo tiles: FP32 / bf16, no split-K");
+    constexpr int TW = NT * 16, TH = WAVES;
+    int t_img = 0, t_y0 = 0, t_x0 = 0;
+    if constexpr (kTile) {
+        const int bxn = (a.Wg + TW - 1) / TW, byn = (a.Hg + TH - 1) / TH;
+        t_img = tile / (bxn * byn);
+        const int rem = tile - t_img * (bxn * byn);
+        t_y0 = (rem / bxn) * TH;
+        t_x0 = (rem - (rem / bxn) * bxn) * TW;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) {
-        const int p = pix0 + t * 16 + l16;
-        pv[t] = p < total;
-        const int q = pv[t] ? p : 0;
-        img[t] = q / HWg;
-        const int r = q - img[t] * HWg;
-        gy[t] = r / a.Wg;
-        gx[t] = r - gy[t] * a.Wg;
+        for (int t = 0; t < NT; ++t) {
+            const int y = t_y0 + wave, x = t_x0 + t * 16 + l16;
+            pv[t] = t_img < a.n && y < a.Hg && x < a.Wg;
+            img[t] = pv[t] ? t_img : 0;
+            gy[t] = pv[t] ? y : 0;
+            gx[t] = pv[t] ? x : 0;
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const int p = pix0 + t * 16 + l16;
+            pv[t] = p < total;
+            const int q = pv[t] ? p : 0;
+            img[t] = q / HWg;
+            const int r = q - img[t] * HWg;
+            gy[t] = r / a.Wg;
+            gx[t] = r - gy[t] * a.Wg;
+        }
     }
 
     f4 acc[MT][NT];
@@ -758,9 +781,83 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             if (k0 + 1 < nk) step(k0 + 1, J1{}, true);
         }
     }
-    Frag Ab[(kALds || kALdsX) ? 1 : P][MT];
-    BRaw Bb[(kALds || kALdsX) ? 1 : P][NT];
-    if constexpr (!kALds && !kALdsX) {
+    if constexpr (kTile) {
+        // Per channel slice (KCH channels, 64 bytes per pixel) the block
+        // stages its (TH + 2) x (TW + 2) halo tile and the slice's weights of
+        // up to 9 taps in LDS: every input pixel is fetched once per block
+        // instead of once per tap.  The next slice is fetched into registers
+        // while the taps of this one run (no global load inside the tap loop),
+        // double-buffered, one barrier per slice.  Layout, 16 words a row:
+        // [halo pixel (hr, hc)] then [tap][weight row].
+        constexpr int HC = TW + 2, HR = TH + 2;
+        constexpr int NHALO = HR * HC;                      // staged pixels
+        constexpr int NROWS = NHALO + 9 * MT * 16;          // plus weight rows
+        constexpr int PIECES = NROWS * 4;                   // 16-byte pieces
+        constexpr int SPT = (PIECES + 255) / 256;
+        static_assert(WAVES == 4, "one block row per wave, 256 threads");
+        static_assert(KCH * (int)sizeof(Elem) == 64, "64-byte channel slices");
+        static_assert(2 * NROWS * 16 <= kSmemWords, "tile fits the LDS buffer");
+        const int tid = threadIdx.x;
+        u32x4 rt[SPT];
+        auto t_gload = [&](int kc) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const int q = tid + i * 256;
+                const int row = q >> 2, c4 = q & 3;
+                const void* src = a.zero;
+                if (row < NHALO) {
+                    const int hr = row / HC, hc = row - (row / HC) * HC;
+                    const int y = t_y0 + hr - 1, x = t_x0 + hc - 1;
+                    if (t_img < a.n && y >= 0 && y < a.Hin && x >= 0 && x < a.Win)
+                        src = static_cast<const Elem*>(a.in) + (((long)t_img * a.Hin + y) * a.Win + x) * CIN + kc * KCH +
+                              c4 * (16 / (int)sizeof(Elem));
+                } else if (row < NROWS) {
+                    const int wr = row - NHALO, t = wr / (MT * 16), r = wr - (wr / (MT * 16)) * (MT * 16);
+                    if (t < ntaps)
+                        src = wbase + ((long)t * CoP + co0 + r) * CIN + kc * KCH + c4 * (16 / (int)sizeof(WElem));
+                }
+                if (PIECES % 256 == 0 || q < PIECES) rt[i] = *reinterpret_cast<const u32x4*>(src);
+            }
+        };
+        auto t_store = [&](int buf) __attribute__((always_inline)) {
+#pragma unroll
+            for (int i = 0; i < SPT; ++i) {
+                const int q = tid + i * 256;
+                if (PIECES % 256 == 0 || q < PIECES) *reinterpret_cast<u32x4*>(&smem[buf * NROWS * 16 + q * 4]) = rt[i];
+            }
+        };
+        t_gload(0);
+        t_store(0);
+        __syncthreads();
+        const int nkc = KC;                                 // channel slices
+        for (int kc = 0; kc < nkc; ++kc) {
+            if (kc + 1 < nkc) t_gload(kc + 1);
+            const uint32_t* T = smem + (kc & 1) * NROWS * 16;
+#pragma unroll 1
+            for (int t = 0; t < ntaps; ++t) {
+                const int tv = __builtin_amdgcn_readlane(tapv, t);
+                const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
+                Frag A[MT];
+#pragma unroll
+                for (int mt = 0; mt < MT; ++mt)
+                    A[mt] = __builtin_bit_cast(Frag, *reinterpret_cast<const u32x4*>(
+                                                         &T[(NHALO + t * MT * 16 + mt * 16 + l16) * 16 + kg * 4]));
+                BRaw B[NT];
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    B[nt] = __builtin_bit_cast(BRaw, *reinterpret_cast<const u32x4*>(
+                                                         &T[((wave + 1 + dy) * HC + nt * 16 + l16 + 1 + dx) * 16 + kg * 4]));
+                compute(A, B);
+            }
+            if (kc + 1 < nkc) {
+                t_store((kc + 1) & 1);                      // its last readers were slice kc - 1
+                __syncthreads();
+            }
+        }
+    }
+    Frag Ab[(kALds || kALdsX || kTile) ? 1 : P][MT];
+    BRaw Bb[(kALds || kALdsX || kTile) ? 1 : P][NT];
+    if constexpr (!kALds && !kALdsX && !kTile) {
 #pragma unroll
     for (int j = 0; j < P - 1; ++j)
         if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
@@ -1171,6 +1268,7 @@ static const KernelEntry kEntries[] = {
     LIC_KG(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KG(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_K(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_K(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    LIC_K(LIC_GS3, 128, 1, 4, 4, LD_TILE, EP_RGB), LIC_K(LIC_GS3, 192, 1, 4, 4, LD_TILE, EP_RGB),
     LIC_KX(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KX(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KX(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KX(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KX(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KX(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
@@ -1190,6 +1288,7 @@ static const KernelEntry kEntries[] = {
     LIC_KGB(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGB(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGB(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
+    LIC_KB(LIC_GS3, 128, 1, 4, 4, LD_TILE, EP_RGB), LIC_KB(LIC_GS3, 192, 1, 4, 4, LD_TILE, EP_RGB),
     LIC_KB(LIC_GA1, 128, 8, 1, 4, LD_F32, EP_GDN), LIC_KB(LIC_GA2, 128, 8, 1, 4, LD_F32, EP_GDN),
     LIC_KB(LIC_GS0, 192, 8, 1, 4, LD_I8, EP_IGDN), LIC_KB(LIC_GS1, 128, 8, 1, 4, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS2, 128, 8, 1, 4, LD_F32, EP_IGDN),

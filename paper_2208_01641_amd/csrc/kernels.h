@@ -30,6 +30,7 @@ enum { TAG_DT1 = 32, TAG_DT2 = 33, TAG_DT3 = 34, TAG_DB2 = 35, TAG_DB3 = 36 };
 // What the tile policy needs to know of a packed layer.
 struct ConvShape {
     int tag, ld, ep, dt, cin, cop, nphase;
+    int halo1 = 0;     // stride-1 grid, every tap within one pixel (halo-tile loader allowed)
 };
 
 // Picks the tile configuration (split-K for small grids) from policy_pixels

@@ -391,6 +391,10 @@ int Codec::build_layers(const ParamMap& P)
         for (size_t i = 0; i < ph.size(); ++i) ph[i].woff = (int64_t)pm.off[i];
         HIP_TRY(hipMemcpy(L.d_ph, ph.data(), ph.size() * sizeof(PhaseDesc), hipMemcpyHostToDevice));
         L.host_ph = ph;
+        L.halo1 = sp.ld != LD_RGB;
+        for (const PhaseDesc& d : ph)
+            for (int t = 0; t < d.ntaps; ++t)
+                if (d.dy[t] < -1 || d.dy[t] > 1 || d.dx[t] < -1 || d.dx[t] > 1) L.halo1 = false;
         std::vector<float> bias(L.cop, 0.0f);
         for (int r = 0; r < L.cop; ++r)
             if (pm.bias_idx[r] >= 0) bias[r] = (float)b[pm.bias_idx[r]];
@@ -484,7 +488,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.rscale = L.d_rscale;
     a.out_q = kActQ;
 
-    const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase};
+    const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase, L.halo1 && g.s_in == 1 ? 1 : 0};
     return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp, chosen);
 }
 
@@ -512,11 +516,17 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
             else key.ksplit = 4;
         }
     } else if (L.ep == EP_RGB) {
-        // every row of the transposed convolution to 3 channels in one wave
+        // every row of the transposed convolution to 3 channels in one wave;
+        // halo tiles staged per block when the taps allow
         key.mt = L.cop / 16;
         key.nt = 4;
         key.waves = 4;
         a.ncog = 1;
+        if (L.halo1 && L.ld == LD_F32) {
+            KernelKey kt = key;
+            kt.ld = LD_TILE;
+            if (kernel_available(kt)) key = kt;
+        }
     } else {
         // 64-channel x 32-pixel wave tiles; when the grid of one image gives
         // fewer than 2 waves per SIMD, split K over 4 or 8 waves of a block;
@@ -546,7 +556,10 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
         }
     }
     const long per_block = (long)(key.waves / key.ksplit) * key.nt * 16;
-    const long tiles = (pixels + per_block - 1) / per_block;
+    // halo tiles: one block per key.waves grid rows x 16 key.nt pixels
+    const long tiles = key.ld == LD_TILE
+                           ? (long)a.n * ((a.Hg + key.waves - 1) / key.waves) * ((a.Wg + 16 * key.nt - 1) / (16 * key.nt))
+                           : (pixels + per_block - 1) / per_block;
     const long nblocks = tiles * L.nphase * a.ncog;
     if (nblocks <= 0 && !chosen) return LIC_OK;
     if (nblocks > (1L << 30)) { *errp = "launch too large"; return LIC_E_BUDGET; }
