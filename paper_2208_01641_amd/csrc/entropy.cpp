@@ -116,14 +116,26 @@ void TableSet::init(int n, const uint32_t* f, bool with_lut)
         }
         start[(size_t)t * (kNumSym + 1) + kNumSym] = s;
     }
-    lut.clear();
+    // Division by an invariant integer through its reciprocal: with
+    // r = ceil(2^64 / f), x r / 2^64 exceeds x / f by less than x / 2^64 <
+    // 2^-32, while the fraction of x / f is at most 1 - 1/f <= 1 - 2^-16, so
+    // the high word of x r is exactly floor(x / f) for every x < 2^32.
+    rcp.assign((size_t)n * kNumSym, 0);
+    for (size_t i = 0; i < rcp.size(); ++i) {
+        const uint64_t fi = freq[i];
+        if (fi > 1) rcp[i] = (~0ull) / fi + 1;     // ceil(2^64 / f) for f >= 2
+    }
+    bucket.clear();
     if (with_lut) {
-        lut.resize((size_t)n << kPrecBits);
+        bucket.resize((size_t)n * kBuckets);
         for (int t = 0; t < n; ++t) {
-            uint8_t* L = lut.data() + ((size_t)t << kPrecBits);
             const uint32_t* st = start.data() + (size_t)t * (kNumSym + 1);
-            for (int a = 0; a < kNumSym; ++a)
-                memset(L + st[a], a, st[a + 1] - st[a]);
+            int a = 0;
+            for (int b = 0; b < kBuckets; ++b) {
+                const uint32_t slot = (uint32_t)b << kBucketShift;
+                while (st[a + 1] <= slot) ++a;
+                bucket[(size_t)t * kBuckets + b] = (uint8_t)a;
+            }
         }
     }
 }
@@ -137,7 +149,7 @@ struct Writer {
     bool ok = true;
 };
 
-inline void enc_put(uint32_t& x, uint32_t f, uint32_t st, Writer& w)
+inline void enc_put(uint32_t& x, uint32_t f, uint32_t st, uint64_t rcp, Writer& w)
 {
     const uint32_t limit = ((kRansLow >> kPrecBits) << 8) * f;   // 2^15 f
     while (x >= limit) {
@@ -145,7 +157,9 @@ inline void enc_put(uint32_t& x, uint32_t f, uint32_t st, Writer& w)
         w.base[--w.pos] = (uint8_t)x;
         x >>= 8;
     }
-    x = ((x / f) << kPrecBits) + (x % f) + st;
+    // (x / f) 2^16 + x mod f + st = x + st + (x / f)(2^16 - f)
+    const uint32_t q = f == 1 ? x : (uint32_t)(((unsigned __int128)x * rcp) >> 64);
+    x = x + st + q * ((1u << kPrecBits) - f);
 }
 
 inline long enc_finish(uint32_t x, Writer& w, size_t cap)
@@ -163,8 +177,12 @@ inline long enc_finish(uint32_t x, Writer& w, size_t cap)
 
 inline int find_symbol(const TableSet& T, int t, uint32_t slot)
 {
-    if (!T.lut.empty()) return T.lut[((size_t)t << kPrecBits) + slot];
     const uint32_t* st = T.start.data() + (size_t)t * (kNumSym + 1);
+    if (!T.bucket.empty()) {
+        int a = T.bucket[(size_t)t * kBuckets + (slot >> kBucketShift)];
+        while (st[a + 1] <= slot) ++a;
+        return a;
+    }
     // largest a with st[a] <= slot
     int lo = 0, hi = kNumSym - 1;
     while (lo < hi) {
@@ -182,7 +200,8 @@ long encode_impl(const int8_t* sym, long n, const TableSet& T, uint8_t* out, siz
     for (long i = n - 1; i >= 0; --i) {
         const int t = tab_of(i);
         const int a = (int)sym[i] - kSymMin;
-        enc_put(x, T.freq[(size_t)t * kNumSym + a], T.start[(size_t)t * (kNumSym + 1) + a], w);
+        const size_t k = (size_t)t * kNumSym + a;
+        enc_put(x, T.freq[k], T.start[(size_t)t * (kNumSym + 1) + a], T.rcp[k], w);
         if (!w.ok) return -1;
     }
     return enc_finish(x, w, cap);

@@ -13,6 +13,8 @@ constexpr int kNumSym = 129;          // symbols -64..64, stored as value + 64
 constexpr int kSymMin = -64;
 constexpr int kPrecBits = 16;         // frequencies sum to 2^16
 constexpr uint32_t kRansLow = 1u << 23;
+constexpr int kBucketShift = 6;        // decoder buckets of 64 slots
+constexpr int kBuckets = 1 << (kPrecBits - kBucketShift);
 constexpr int kDensityParams = 43;    // raw parameters of one channel's density
 constexpr int kScales = 64;
 
@@ -36,7 +38,11 @@ struct TableSet {
     int ntab = 0;
     std::vector<uint32_t> freq;    // [ntab][129]
     std::vector<uint32_t> start;   // [ntab][130]
-    std::vector<uint8_t> lut;      // [ntab][65536] (empty: binary search)
+    // encoder: x / f as the high word of x * rcp (rcp = ceil(2^64 / f), 0 for f = 1)
+    std::vector<uint64_t> rcp;     // [ntab][129]
+    // decoder: symbol holding the first slot of each 64-slot bucket (empty:
+    // binary search over start); a short forward scan finishes the search
+    std::vector<uint8_t> bucket;   // [ntab][1024]
     void init(int n, const uint32_t* f, bool with_lut);
 };
 
