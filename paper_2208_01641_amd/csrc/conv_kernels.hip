@@ -214,7 +214,10 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // (GDN blocks of four unsplit waves keep idle waves: they take part in the
     // barriers of the shared weight and gamma staging)
     constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
-    constexpr bool kALdsEarly = kGLds && DT != DT_FP8 && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0;
+    // (e4m3: only for e4m3 activation inputs with 8 row blocks; the symbol
+    // loader's conversion and 12 row blocks do not fit the registers)
+    constexpr bool kALdsEarly = kGLds && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0 &&
+                                (DT != DT_FP8 || (LD == LD_F32 && MT == 8));
     // the split-FP32 form stages the (three times larger) weight tiles of its
     // GDN layers in LDS: a 2-stage ring filled from one register set (other
     // shapes would load them per wave)
@@ -223,7 +226,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // one LDS buffer for the staged weight ring of the K loop and, after it,
     // the staged gamma slices of the GDN epilogue
     constexpr int kGP = (DT == DT_F32 || DT == DT_F32X) ? 3 : 2;   // bf16 parts of gamma
-    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * 20 : kALdsX ? 2 * MT * 16 * 52
+    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * (DT == DT_FP8 ? 36 : 20) : kALdsX ? 2 * MT * 16 * 52
                           : LD == LD_TILE ? 2 * ((WAVES + 2) * (NT * 16 + 2) + 9 * MT * 16) * 16 : 0;
     constexpr int kGWords = kGLds ? 2 * kGP * MT * 16 * 16 : 0;
     constexpr int kSmemWords = (kAWords > kGWords ? kAWords : kGWords) > 0 ? (kAWords > kGWords ? kAWords : kGWords) : 4;
@@ -624,20 +627,34 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     constexpr bool kALds = kALdsEarly;
     if constexpr (kALds) {
         static_assert(P == 3, "the shared-weight loop is written for a 3-deep ring");
-        constexpr int NPIECE = MT / 4;                      // 16-byte pieces per thread per chunk
-        constexpr int AROW = 20;                            // LDS row pitch in dwords (64 + 16 bytes)
+        // a chunk row is 64 bytes (FP32 / bf16) or 128 bytes (e4m3: the
+        // flattened (tap, channel) chunk, 32 bytes per lane group), padded by
+        // 16 bytes in LDS so the 16 rows of one fragment load hit distinct banks
+        constexpr int RB = KCH * (int)sizeof(WElem);
+        constexpr int PPR = RB / 16;                        // 16-byte pieces per row
+        constexpr int AROW = RB / 4 + 4;                    // LDS row pitch in dwords
         constexpr int ROWS = MT * 16;
+        constexpr int NPIECE = ROWS * PPR / 256;            // pieces per thread per chunk
+        static_assert(ROWS * PPR % 256 == 0, "whole pieces per thread");
         uint32_t* const As = smem;                          // [3][ROWS][AROW]
         static_assert(3 * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
         const int tid = threadIdx.x;
-        int a_t = 0, a_kc = 0;
+        int a_t = 0, a_kc = 0, a_k = 0;
         auto a_gload = [&](u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
 #pragma unroll
             for (int i = 0; i < NPIECE; ++i) {
-                const int q = tid + i * 256, row = q >> 2, c16 = q & 3;
-                const WElem* src = wbase + ((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH + c16 * (16 / (int)sizeof(WElem));
+                const int q = tid + i * 256, row = q / PPR, c16 = q - (q / PPR) * PPR;
+                const void* src;
+                if constexpr (DT == DT_FP8) {
+                    // flattened position of the piece; past the last tap: zeros
+                    const int f = a_k * KCH + c16 * 16, t = f / CIN, c = f - (f / CIN) * CIN;
+                    src = t < ntaps ? static_cast<const void*>(wbase + ((long)t * CoP + co0 + row) * CIN + c) : a.zero;
+                } else {
+                    src = wbase + ((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH + c16 * (16 / (int)sizeof(WElem));
+                }
                 r[i] = *reinterpret_cast<const u32x4*>(src);
             }
+            ++a_k;
             if (++a_t == ntaps) {
                 a_t = 0;
                 ++a_kc;
@@ -646,16 +663,26 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         auto a_store = [&](int stage, const u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
 #pragma unroll
             for (int i = 0; i < NPIECE; ++i) {
-                const int q = tid + i * 256, row = q >> 2, c16 = q & 3;
+                const int q = tid + i * 256, row = q / PPR, c16 = q - (q / PPR) * PPR;
                 *reinterpret_cast<u32x4*>(&As[(stage * ROWS + row) * AROW + c16 * 4]) = r[i];
             }
         };
         auto a_frag = [&](int stage, Frag (&A)[MT]) __attribute__((always_inline)) {
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
-                const u32x4 u = *reinterpret_cast<const u32x4*>(&As[(stage * ROWS + mt * 16 + l16) * AROW + kg * 4]);
-                A[mt] = __builtin_bit_cast(Frag, u);
+                const uint32_t* src = &As[(stage * ROWS + mt * 16 + l16) * AROW + kg * (RB / 16)];
+                if constexpr (DT == DT_FP8) {
+                    const u32x4 lo = *reinterpret_cast<const u32x4*>(src), hi = *reinterpret_cast<const u32x4*>(src + 4);
+                    A[mt] = i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3], (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+                } else {
+                    A[mt] = __builtin_bit_cast(Frag, *reinterpret_cast<const u32x4*>(src));
+                }
             }
+        };
+        // pixels of chunk kk (the e4m3 loader takes the flat chunk index)
+        auto loadBs = [&](int kk, BRaw (&B)[NT]) __attribute__((always_inline)) {
+            if constexpr (DT == DT_FP8) loadB8(kk, B);
+            else cursor_loadB(B);
         };
         BRaw Bb[P][NT];
         u32x4 ra[3][NPIECE];
@@ -665,7 +692,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         if (2 < nk) a_gload(ra[2]);
 #pragma unroll
         for (int j = 0; j < P - 1; ++j)
-            if (j < nk) cursor_loadB(Bb[j]);
+            if (j < nk) loadBs(j, Bb[j]);
         if (0 < nk) a_store(0, ra[0]);
         if (1 < nk) a_store(1, ra[1]);
         if (3 < nk) a_gload(ra[0]);
@@ -674,7 +701,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         // (j is a compile-time constant so that every ring index is static)
         auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
-            if (!guard || k + P - 1 < nk) cursor_loadB(Bb[(j + P - 1) % P]);
+            if (!guard || k + P - 1 < nk) loadBs(k + P - 1, Bb[(j + P - 1) % P]);
             Frag A[MT];
             a_frag(j, A);
             compute(A, Bb[j]);
