@@ -32,6 +32,7 @@ struct LayerGPU {
     bool rows = false;                 // 4 phases as GEMM rows (transposed conv to 3 channels)
     int nphase = 1;
     bool halo1 = false;                // every tap within one pixel of a stride-1 grid
+    bool out_e4m3 = false;             // bf16 GEMM storing e4m3 activations (e4m3 form, image layer)
     std::vector<PhaseDesc> host_ph;
     PhaseDesc* d_ph = nullptr;
     uint8_t* d_w = nullptr;            // packed weights (float, bf16 or e4m3)

@@ -78,6 +78,8 @@ struct ConvArgs {
     int kk, pad;             // LD_RGB kernel size and padding
     const float* rscale;     // DT_FP8: per packed row, weight scale x input scale
     float out_q;             // DT_FP8: activations are stored as e4m3(out_q * value)
+    int out_e4m3;            // DT_BF16 kernels: store e4m3(out_q * value) instead of bf16
+                             // (the e4m3 form's image layer runs on bf16 operands)
 };
 
 }  // namespace lic

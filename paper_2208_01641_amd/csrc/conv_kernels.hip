@@ -526,6 +526,10 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             const float q = a.out_q;
             *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
                 e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
+        } else if (a.out_e4m3) {
+            const float q = a.out_q;
+            *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
+                e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
         } else {
             bf16x4 h;
 #pragma unroll
@@ -1320,7 +1324,6 @@ static const KernelEntry kEntries[] = {
     LIC_KB(LIC_GS0, 192, 8, 1, 4, LD_I8, EP_IGDN), LIC_KB(LIC_GS1, 128, 8, 1, 4, LD_F32, EP_IGDN),
     LIC_KB(LIC_GS2, 128, 8, 1, 4, LD_F32, EP_IGDN),
     // e4m3 operands (precision form): g_a and g_s
-    LIC_KF(LIC_GA0, 128, 8, 2, 4, LD_RGB, EP_GDN), LIC_KF(LIC_GA0, 128, 12, 1, 4, LD_RGB, EP_GDN),
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),

@@ -307,6 +307,10 @@ int Codec::build_layers(const ParamMap& P)
         // form; h_a and h_s always run in FP32 (fixed-order scale index)
         const bool is_gags = sp.id <= LIC_GA3 || sp.id >= LIC_GS0;
         L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
+        // the e4m3 form's image layer: bf16 operands (a K of 75 is one
+        // chunk; pixel values keep 8 bits), e4m3 activations out
+        L.out_e4m3 = L.dt == DT_FP8 && sp.ld == LD_RGB;
+        if (L.out_e4m3) L.dt = DT_BF16;
         // 75 (tap, channel) pairs in whole K chunks
         const int krgb = L.dt == DT_FP8 ? 128 : 96;
         L.cin = sp.ld == LD_RGB ? krgb : ci;
@@ -487,6 +491,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.pad = L.k / 2;
     a.rscale = L.d_rscale;
     a.out_q = kActQ;
+    a.out_e4m3 = L.out_e4m3 ? 1 : 0;
 
     const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase, L.halo1 && g.s_in == 1 ? 1 : 0};
     return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp, chosen);

@@ -2,7 +2,8 @@
 
 The GEMM operands are e4m3: weights w8 = e4m3(w / s_row) with one FP32 scale
 per output row (s_row = max |w| of the row / 448), activations between layers
-stored as e4m3(8 x value), the image and y_hat converted in the loaders.
+stored as e4m3(8 x value), y_hat converted in the loader; the image layer
+runs on bf16 operands and stores e4m3 activations.
 Products of e4m3 values are exact in FP32, so the oracle runs in FP64 on the
 same dequantised operands: what remains is FP32 accumulation (float outputs
 within 1e-4) and, for layers that store e4m3 activations, one e4m3 rounding
@@ -17,6 +18,7 @@ import oracle
 import synth
 from gpu_util import chw, layer_out_shape, make_codec, rel_err
 from test_gpu_codec import _expected_stream
+from test_gpu_precision import bf16
 
 pytestmark = pytest.mark.gpu
 
@@ -92,7 +94,8 @@ def test_fp8_analysis_layers(torch_dev, N, M, H, W):
     xd = torch.from_numpy(x)[None].cuda()
     a = torch.empty((1,) + layer_out_shape("GA0", H, W, N, M), device="cuda", dtype=torch.uint8)
     c.run_layer("GA0", 1, H, W, xd, a)
-    ref = oracle.gdn(oracle.conv2d(e4m3(oracle.pad64(x)), w_fp8(P["ga0.w"], "conv"), P["ga0.b"], 2, 2),
+    # the image layer runs on bf16 operands and stores e4m3 activations
+    ref = oracle.gdn(oracle.conv2d(bf16(oracle.pad64(x)), bf16(P["ga0.w"]), P["ga0.b"], 2, 2),
                      P["ga0.beta"], P["ga0.gamma"])
     assert np.max(np.abs(ref)) * Q < 448
     assert rel_err(act(a), ref) < FP8_OUT_TOL

@@ -59,8 +59,11 @@ class Form:
             return bf16(w)
         return w_fp8(w, kind)
 
-    def image(self, x):
-        return {0: lambda v: v, 1: bf16, 2: e4m3}[self.prec](x)
+    def image(self, x):             # the image layer of the e4m3 form runs on bf16 operands
+        return x if self.prec == 0 else bf16(x)
+
+    def w_first(self, w):
+        return w if self.prec == 0 else bf16(w)
 
     def yhat(self, sym):
         return e4m3(sym) if self.prec == 2 else sym
@@ -110,7 +113,8 @@ def test_analysis_sampled(chain):
     for i, L in enumerate(("GA0", "GA1", "GA2")):
         out = f.values(o[L])
         pts = _points(out.shape[1], out.shape[2], np.random.default_rng(11 + i))
-        ref = oracle.conv2d_points(src, f.w(P[f"ga{i}.w"], "conv"), P[f"ga{i}.b"], 2, 2, pts)
+        w = f.w_first(P["ga0.w"]) if i == 0 else f.w(P[f"ga{i}.w"], "conv")
+        ref = oracle.conv2d_points(src, w, P[f"ga{i}.b"], 2, 2, pts)
         ref = oracle.gdn(ref.T, P[f"ga{i}.beta"], P[f"ga{i}.gamma"]).T
         err = _rel(_sampled(out, pts), ref)
         print(f"{L}: max error / max |ref| = {err:.2e}")
