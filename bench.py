@@ -79,6 +79,37 @@ def traffic_for(layer):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def rans_rate(blob, n=737280, seed=5):
+    """Host rANS speed on one core: one 720p frame's worth of y symbols (N=128
+    M=192: 48 x 80 x 192) with the codec's Gaussian tables and scale indices
+    spread over the table, through the C ABI's encoder and decoder."""
+    import numpy as np
+
+    from paper_2208_01641_amd import rans_decode, rans_encode
+    from paper_2208_01641_amd._lib import lib
+
+    freq = np.zeros(64 * 129, np.uint32)
+    buf = np.frombuffer(blob, np.uint8).copy()
+    k = lib.lic_blob_tables(buf.ctypes.data, len(blob), 1, freq.ctypes.data, freq.size, None, 0)
+    assert k == freq.size, k
+    freq = freq.reshape(64, 129)
+    rng = np.random.default_rng(seed)
+    tab = rng.integers(0, 40, n).astype(np.uint8)
+    cum = np.cumsum(freq, axis=1)
+    slot = rng.integers(0, 1 << 16, n)
+    sym = np.array([np.searchsorted(cum[t], s, side="right") for t, s in zip(tab[:4096], slot[:4096])], np.uint8)
+    sym = np.resize(sym, n)
+    tab = np.resize(tab[:4096], n)
+    t0 = time.perf_counter()
+    data = rans_encode(sym, tab, freq)
+    t1 = time.perf_counter()
+    back = rans_decode(data, tab, freq, n)
+    t2 = time.perf_counter()
+    assert np.array_equal(back, sym)
+    return {"symbols": n, "encode_msym_per_s_per_core": round(n / (t1 - t0) / 1e6, 1),
+            "decode_msym_per_s_per_core": round(n / (t2 - t1) / 1e6, 1), "bits_per_symbol": round(8 * len(data) / n, 3)}
+
+
 def cpu_baseline(x_np, P, blob, N, M):
     """The FP64 oracle on the host cores, on a 384x640 crop of one frame
     (a quarter of the padded 768x1280 area), scaled to frames/s."""
@@ -142,6 +173,8 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
             layers[L] = {"avg_us": 1e3 * per_launch, "launches": n, "tflops": flops / (per_launch * 1e-3) / 1e12,
                          "flops_per_launch": flops, "form": codec.layer_kernel(L, H, W)[0]}
     mse = torch.mean((out[:steps] - frames[:steps]) ** 2, dim=(1, 2, 3))
+    # GPU work per frame: the summed kernel time of every timed layer
+    kernel_ms = sum(codec.layer_time(L)[0] for L in timed_layers) / (steps * batch)
     res = {
         "fps": steps / dt,
         "ms_per_step": 1e3 * dt / steps,
@@ -152,6 +185,7 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
         "gpu_busy_s": st["gpu_busy_s"],
         "cpu_busy_s": st["cpu_busy_s"],
         "layers": layers,
+        "kernel_ms_per_frame": kernel_ms,
     }
     codec.close()
     x0 = frames[0].cpu().numpy()
@@ -400,6 +434,8 @@ def main():
     dtype = {0: "f32", 1: "bf16", 2: "fp8"}[prec]
     H, W, K, Wm = args.height, args.width, args.steps, args.warmup
     N, M = 128, 192
+    # (the headline run times two layers only: events between every launch
+    # perturb the pipelined run; the one-frame-in-flight variant times all)
     timed = list(LAYERS) if args.all_layers else ["GA1", "GS2"]
     main_res, x0, P, blob = run_workload(
         H=H, W=W, N=N, M=M, precision=prec, batch=1, steps=K, warmup=Wm, threads=threads,
@@ -451,8 +487,13 @@ def main():
         var = {}
         common = dict(threads=threads, slices=args.slices, zero_copy=args.zero_copy, timed_layers=["GA1", "GS2"])
         r, _, _, _ = run_workload(H=720, W=1280, N=128, M=192, precision=0, batch=1, steps=60, warmup=5,
-                                  inflight=1, **common)
+                                  inflight=1, **dict(common, timed_layers=list(LAYERS)))
         var["fp32_720p_one_frame_in_flight"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms", "psnr_db", "bpp")})
+        # GPU-only bound: frames/s if the GPU ran one frame's kernels back to
+        # back with nothing else (no entropy coding, no overlap)
+        var["fp32_720p_one_frame_in_flight"]["gpu_kernel_ms_per_frame"] = round(r["kernel_ms_per_frame"], 4)
+        var["fp32_720p_one_frame_in_flight"]["gpu_only_fps"] = round(1e3 / r["kernel_ms_per_frame"], 1)
+        var["rans_one_core"] = rans_rate(blob)
         # ladder rungs: symbols and indices through device buffers and async
         # copies instead of zero-copy stores; frames in pinned host memory
         zc = dict(common, zero_copy=0)

@@ -370,7 +370,7 @@ int lic_rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n, c
     for (long i = 0; i < n; ++i)
         if (tab[i] >= ntab) return LIC_E_ARG;
     lic::TableSet T;
-    T.init(ntab, freq, false);
+    T.init(ntab, freq, true);
     for (int t = 0; t < ntab; ++t)
         if (T.start[(size_t)t * (lic::kNumSym + 1) + lic::kNumSym] != (1u << lic::kPrecBits)) return LIC_E_ARG;
     std::vector<int8_t> v(n);
