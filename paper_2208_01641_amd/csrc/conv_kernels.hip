@@ -1337,6 +1337,7 @@ static const KernelEntry kEntries[] = {
     LIC_K2B(TAG_DT1, 192, LD_I8, EP_RELU), LIC_K2B(TAG_DT1, 320, LD_I8, EP_RELU),
     LIC_K2(TAG_DT2, 64, LD_F32, EP_RELU), LIC_K2B(TAG_DT2, 64, LD_F32, EP_RELU),
     LIC_K(TAG_DT3, 64, 3, 4, 4, LD_F32, EP_RGB), LIC_KB(TAG_DT3, 64, 3, 4, 4, LD_F32, EP_RGB),
+    LIC_K(TAG_DT3, 64, 3, 4, 4, LD_TILE, EP_RGB), LIC_KB(TAG_DT3, 64, 3, 4, 4, LD_TILE, EP_RGB),
     LIC_K2(TAG_DB2, 64, LD_F32, EP_MASK), LIC_K2(TAG_DB3, 192, LD_RGB, EP_MASK),
 };
 

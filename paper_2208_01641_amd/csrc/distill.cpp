@@ -59,6 +59,11 @@ int DistillNet::build_layer(Layer& L, int tag, int ld, int ep, int dt, PackKind 
 {
     const PackMap pm = pack_map(kind, ci, co, k, s, p, w_deconv, kimg);
     L.shape = ConvShape{tag, ld, ep, dt, pm.cin, pm.cop, (int)pm.ph.size()};
+    // every tap within one pixel of the (stride-1) phase grid: halo tiles allowed
+    L.shape.halo1 = ld != LD_RGB;
+    for (const PhaseDesc& d : pm.ph)
+        for (int t = 0; t < d.ntaps; ++t)
+            if (d.dy[t] < -1 || d.dy[t] > 1 || d.dx[t] < -1 || d.dx[t] > 1) L.shape.halo1 = 0;
     L.co = co;
     L.k = k;
     L.s = s;
