@@ -732,38 +732,87 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         // Split-FP32 weights: per chunk a row holds 32 channels x 3 parts
         // (192 bytes, twelve 16-byte pieces), padded to 208 bytes in LDS so
         // that the 16 rows read by one 16-byte load land in distinct banks.
-        // Chunk k + 1 is fetched into registers (issued before the pixel
-        // prefetch, so waiting for it never waits for those) while chunk k
-        // feeds the matrix cores, then stored to the other stage; one barrier
-        // per chunk.
-        constexpr int PPR = 12;
+        // Chunk k + 1 is loaded into the other stage while chunk k feeds the
+        // matrix cores; one barrier per chunk.  With two pixel tiles per wave
+        // the tiles go from global memory straight into LDS
+        // (global_load_lds_dwordx4: lane L of an instruction fills the 16
+        // bytes at base + 16 L), so no registers and no LDS stores stage
+        // them.  With one pixel tile the matrix work of a chunk is too short
+        // to cover that path's wait, and the chunk is fetched into registers
+        // (issued before the pixel prefetch, so waiting for it never waits
+        // for those) and stored after the chunk's products.
+        constexpr bool kDirect = NT >= 2;
         constexpr int AROW = 52;
         constexpr int ROWS = MT * 16;
-        constexpr int NPIECE = ROWS * PPR / 256;
-        static_assert(ROWS * PPR % 256 == 0, "whole pieces per thread");
         static_assert(2 * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
         uint32_t* const As = smem;                          // [2][ROWS][AROW]
-        const int tid = threadIdx.x;
         int a_t = 0, a_kc = 0;
-        u32x4 ra[NPIECE];
-        auto a_gload = [&]() __attribute__((always_inline)) {
-#pragma unroll
-            for (int i = 0; i < NPIECE; ++i) {
-                const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
-                const WElem* src = wbase + (((long)a_t * CoP + co0 + row) * CIN + a_kc * KCH) * 3 + c * 8;
-                ra[i] = *reinterpret_cast<const u32x4*>(src);
-            }
+        auto a_next = [&]() __attribute__((always_inline)) {
             if (++a_t == ntaps) {
                 a_t = 0;
                 ++a_kc;
             }
         };
-        auto a_store = [&](int stage) __attribute__((always_inline)) {
+        // direct path: a stage is ROWS rows of 13 slots (12 data pieces and
+        // the pad slot); the 64-slot instructions go round-robin to the waves
+        constexpr int SLOTS = ROWS * 13;
+        constexpr int NI = SLOTS / 64;
+        constexpr int NIW = kDirect ? (NI + WAVES - 1) / WAVES : 1;   // instructions per wave
+        static_assert(SLOTS % 64 == 0 && AROW == 52, "whole 64-slot instructions over 208-byte rows");
+        // per-lane element offsets of this wave's slots from the chunk's first
+        // row (fixed over the K loop); the pad slot re-reads its row's first
+        // piece, which lands in the pad and is never read back
+        int soff[NIW];
+        if constexpr (kDirect) {
 #pragma unroll
-            for (int i = 0; i < NPIECE; ++i) {
-                const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
-                *reinterpret_cast<u32x4*>(&As[(stage * ROWS + row) * AROW + c * 4]) = ra[i];
+            for (int u = 0; u < NIW; ++u) {
+                const int q = (u * WAVES + wave) * 64 + lane, row = q / 13, c = q - (q / 13) * 13;
+                soff[u] = row * CIN * 3 + (c < 12 ? c * 8 : 0);
             }
+        }
+        // register path: twelve 16-byte pieces per row, NPIECE per thread
+        constexpr int PPR = 12;
+        constexpr int NPIECE = kDirect ? 1 : ROWS * PPR / 256;
+        static_assert(kDirect || ROWS * PPR % 256 == 0, "whole pieces per thread");
+        const int tid = threadIdx.x;
+        u32x4 ra[NPIECE];
+        // issue the loads of the next chunk (into LDS stage `stage` on the direct path)
+        auto a_fetch = [&](int stage) __attribute__((always_inline)) {
+            const WElem* cb = wbase + ((long)a_t * CoP + co0) * CIN * 3 + a_kc * KCH * 3;
+            if constexpr (kDirect) {
+#pragma unroll
+                for (int u = 0; u < NIW; ++u) {
+                    const int i = u * WAVES + wave;
+                    if (NI % WAVES == 0 || i < NI) {
+#if defined(__HIP_DEVICE_COMPILE__)   // device builtin: the host pass would drop the kernel stub
+                        __builtin_amdgcn_global_load_lds(cb + soff[u], smem + (stage * ROWS * AROW + i * 256), 16, 0, 0);
+#endif
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < NPIECE; ++i) {
+                    const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
+                    ra[i] = *reinterpret_cast<const u32x4*>(cb + row * CIN * 3 + c * 8);
+                }
+            }
+            (void)cb;
+            a_next();
+        };
+        // make the fetched chunk (if `fetched`) visible to every wave; the
+        // LDS side of the direct loads is invisible to the compiler's own
+        // waits, so that path waits for every load of this wave first
+        auto a_publish = [&](int stage, bool fetched) __attribute__((always_inline)) {
+            if constexpr (kDirect) {
+                __builtin_amdgcn_s_waitcnt(0);
+            } else if (fetched) {
+#pragma unroll
+                for (int i = 0; i < NPIECE; ++i) {
+                    const int q = tid + i * 256, row = q / PPR, c = q - (q / PPR) * PPR;
+                    *reinterpret_cast<u32x4*>(&As[(stage * ROWS + row) * AROW + c * 4]) = ra[i];
+                }
+            }
+            __syncthreads();
         };
         BRaw Bb[P][NT];
         // pixels of chunk kk: the gathered loaders walk their cursor, the
@@ -773,15 +822,15 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             else loadB(kk / KC, kk % KC, B);
         };
         // prologue: chunk 0 in LDS, pixels of chunks 0 .. P - 2 in flight
-        if (0 < nk) a_gload();
+        if (0 < nk) a_fetch(0);
 #pragma unroll
         for (int j = 0; j < P - 1; ++j)
             if (j < nk) loadBk(j, Bb[j]);
-        if (0 < nk) a_store(0);
-        __syncthreads();
+        a_publish(0, 0 < nk);
         auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
             constexpr int j = decltype(jc)::value;
-            if (!guard || k + 1 < nk) a_gload();
+            // chunk k + 1 for the other stage (its readers passed the last barrier)
+            if (!guard || k + 1 < nk) a_fetch(1 - j);
             if (!guard || k + P - 1 < nk) loadBk(k + P - 1, Bb[(j + P - 1) % P]);
             BFrag B[NT];
 #pragma unroll
@@ -796,8 +845,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
                 for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = mfma_x(A, B[nt], acc[mt][nt]);
             }
-            if (!guard || k + 1 < nk) a_store(1 - j);
-            __syncthreads();
+            a_publish(1 - j, !guard || k + 1 < nk);
         };
         static_assert(P == 2, "the split-FP32 loop is written for a 2-deep pixel ring");
         int k0 = 0;
