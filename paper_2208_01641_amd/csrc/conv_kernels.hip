@@ -1374,6 +1374,8 @@ static const KernelEntry kEntries[] = {
     // e4m3 operands (precision form): g_a and g_s
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
+    // one 16-pixel group per wave (grids between half and one wave per SIMD)
+    LIC_KF(LIC_GA2, 128, 8, 1, 4, LD_F32, EP_GDN), LIC_KF(LIC_GS0, 192, 8, 1, 4, LD_I8, EP_IGDN),
     LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),
     LIC_KGF(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KGF(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
     LIC_KGF(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
