@@ -1,5 +1,8 @@
-// Implicit-GEMM convolution kernels for CDNA4 (gfx950) on MFMA: FP32
-// operands, or bf16 operands with FP32 accumulation (precision form).
+// Implicit-GEMM convolution kernels for CDNA4 (gfx950) on MFMA, FP32
+// accumulation over four operand forms: FP32 (v_mfma_f32_16x16x4_f32),
+// split-FP32 (each FP32 operand as the exact sum of three bf16 parts, the six
+// part products of order <= 2 on the bf16 matrix cores), bf16, and OCP e4m3
+// with per-row FP32 scales (v_mfma_scale_f32_16x16x128_f8f6f4).
 //
 // One kernel template covers every layer of the analysis / synthesis and
 // hyper transforms (strided 5x5 and 3x3 convolutions, and stride-2 5x5
@@ -21,6 +24,17 @@
 // contracts channel 4g+e.  The D layout then gives each lane 4 consecutive
 // output channels of one pixel, which is exactly the B-operand layout the
 // GDN contraction over channels needs - no data movement between the two.
+// The other forms keep that arrangement with 32 channels per chunk (bf16,
+// split-FP32) or 128 (tap, channel) pairs (e4m3).
+//
+// Data movement: the GDN layers of whole frames stage each K chunk's weight
+// tile once per block in an LDS ring (from registers, or for split-FP32 with
+// two pixel tiles per wave straight from global memory into LDS) and the
+// gamma slices of the epilogue likewise; pixels stay in per-wave register
+// rings.  The stride-1 output layer stages halo tiles (a block's rows of
+// pixels with a one-pixel border) and the weights in LDS per channel slice.
+// Small grids split K over the waves of a block with a fixed-order LDS
+// reduction.
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
