@@ -74,16 +74,19 @@ double or_deconv2d_at(const double* in, int C, int H, int W,
                       const double* w, const double* b, int Co, int k, int s, int p,
                       int o, int i, int j)
 {
+    /* the taps u with (i + p - u) divisible by s are u0, u0 + s, ... with  */
+    /* u0 = (i + p) mod s (likewise v); the others contribute nothing      */
+    const int u0 = (i + p) % s, v0 = (j + p) % s;
     double acc = b ? b[o] : 0.0;
     for (int c = 0; c < C; ++c)
-        for (int u = 0; u < k; ++u) {
+        for (int u = u0; u < k; u += s) {
             int ti = i + p - u;
-            if (ti < 0 || ti % s != 0) continue;
+            if (ti < 0) continue;
             int r = ti / s;
             if (r >= H) continue;
-            for (int v = 0; v < k; ++v) {
+            for (int v = v0; v < k; v += s) {
                 int tj = j + p - v;
-                if (tj < 0 || tj % s != 0) continue;
+                if (tj < 0) continue;
                 int q = tj / s;
                 if (q >= W) continue;
                 acc += w[(((long)c * Co + o) * k + u) * k + v] * in[((long)c * H + r) * W + q];
