@@ -305,6 +305,7 @@ struct Codec {
     float judge_db = 0.0f;                   // fall back when PSNR(full, distilled) < judge_db
     int judge_every = 30;                    // frames between judged frames
     std::atomic<bool> gs_fallback{false};
+    int gs_gen = 0;                          // distilled nets loaded so far (graph cache key)
     std::atomic<long> gs_frames{0}, gs_judged{0};
     double gs_judge_last_db = 0.0;
     float* d_judge_img = nullptr;            // 3 x max_h x max_w
@@ -320,6 +321,7 @@ struct Codec {
     int open_stream(int H, int W, int* id);
     int close_stream(int id);
     int gpu_stage_graph(Task* t, GpuStage& G, int (Codec::*body)(Task*, GpuStage&));
+    void server_drop_graphs(int stage_kind);
 
     Codec();
     ~Codec();

@@ -496,7 +496,11 @@ int Codec::load_distilled(const float* params, size_t n, float judge_psnr_db, in
         h_judge = (float*)host_alloc(sizeof(float));
         if (!d_judge_img || !d_judge_part || !h_judge) { err = "allocation failed"; return LIC_E_NOMEM; }
     }
+    // graphs of the g_s stage captured with the previous net point at its
+    // buffers: drop them before that net is freed
+    server_drop_graphs(ST_GPU_GS);
     distill = std::move(net);
+    gs_gen++;
     judge_db = judge_psnr_db;
     judge_every = every;
     gs_fallback.store(false);

@@ -7,9 +7,9 @@
 // longest, and sends them through the stages as one task, so requests that
 // arrive while others are on the GPU or the entropy workers are admitted as
 // soon as a slot frees up.  Each GPU stage of a serving task can run as a
-// captured HIP graph keyed by (stage, frame size, batch, slot): every
-// pointer inside it is a slot or stage buffer, and the request buffers are
-// copied in and out around the graph.  Streams are admitted against the
+// captured HIP graph keyed by (stage, frame size, batch, slot, synthesis
+// variant): every pointer inside it is a slot or stage buffer, and the
+// request buffers are copied in and out around the graph.  Streams are admitted against the
 // device-memory budget.
 #include <string.h>
 
@@ -46,7 +46,8 @@ struct Server {
     std::condition_variable done_cv;
     std::deque<lic_result> done;
     std::mutex graph_m;
-    std::map<std::tuple<int, int, int, int, int>, hipGraphExec_t> graphs;
+    // (stage, H, W, batch, slot, synthesis variant) -> executable graph
+    std::map<std::tuple<int, int, int, int, int, int>, hipGraphExec_t> graphs;
 };
 
 // Device footprint of one in-flight frame of a stream: input and
@@ -281,14 +282,37 @@ Codec::~Codec()
     for (void* p : host_allocs) (void)hipHostFree(p);
 }
 
+// Destroys the cached graphs of one stage kind (the g_s stage when another
+// distilled net is loaded: its graphs point at the old net's buffers).
+void Codec::server_drop_graphs(int stage_kind)
+{
+    if (!server) return;
+    Server& S = *server;
+    std::lock_guard<std::mutex> g(S.graph_m);
+    for (auto it = S.graphs.begin(); it != S.graphs.end();) {
+        if (std::get<0>(it->first) == stage_kind) {
+            (void)hipGraphExecDestroy(it->second);
+            it = S.graphs.erase(it);
+        } else {
+            ++it;
+        }
+    }
+}
+
 // Runs one GPU stage of a serving task as a captured HIP graph.  The body
 // only touches slot and stage buffers (the request buffers are copied in and
 // out by the caller), so a graph is valid for every task with the same
-// stage, frame size, batch and slot.
+// stage, frame size, batch and slot - and, for the g_s stage, the same
+// synthesis transform: the full g_s (variant 0) or the distilled net loaded
+// as the gs_gen-th one (variant gs_gen), which is part of the key so that a
+// fallback to the full g_s never replays a graph of the distilled net.  The
+// variant is read on the g_s stage's own thread, the only one that sets the
+// fallback.
 int Codec::gpu_stage_graph(Task* t, GpuStage& G, int (Codec::*body)(Task*, GpuStage&))
 {
     Server& S = *server;
-    const auto key = std::make_tuple((int)G.kind, t->route->dims.H, t->route->dims.W, t->nb, t->slot);
+    const int variant = G.kind == ST_GPU_GS && cfg.gs_mode != 0 && distill && !gs_fallback.load() ? gs_gen : 0;
+    const auto key = std::make_tuple((int)G.kind, t->route->dims.H, t->route->dims.W, t->nb, t->slot, variant);
     hipGraphExec_t exec = nullptr;
     {
         std::lock_guard<std::mutex> g(S.graph_m);
