@@ -143,3 +143,58 @@ def test_slot_reuse_with_varying_batches_drains_and_closes(torch_dev):
     assert sorted(dtick[r["ticket"]] for r in res) == list(range(len(order)))
     assert all(r["status"] == 0 for r in res)
     c.close()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", [1, 0])
+def test_mixed_resolutions_at_serving_sizes_equal_alone(torch_dev, precision):
+    """The serving mix at its real frame sizes (360p, 720p and 1080p streams
+    in the ratio 2:1:1; whole-frame kernels, batches of up to 4, captured
+    graphs): every bitstream and reconstruction equals the frame coded alone
+    (eager, batch 1), on the first round and on a round that replays the
+    graphs."""
+    torch = torch_dev
+    sizes = [(360, 640), (360, 640), (720, 1280), (1080, 1920)]
+    alone, _ = make_codec(1, 128, 192, precision=precision, max_h=1080, max_w=1920, y_slices=4, entropy_threads=8,
+                          max_in_flight=2)
+    srv, _ = make_codec(1, 128, 192, precision=precision, max_h=1080, max_w=1920, y_slices=4, entropy_threads=8,
+                        max_in_flight=4, max_batch=4, use_graphs=1)
+    nf = 3
+    frames = {s: [torch.from_numpy(synth.frame_sinusoid(H, W, t=t, stream=30 + s)).cuda() for t in range(nf)]
+              for s, (H, W) in enumerate(sizes)}
+    ref_bits, ref_img = {}, {}
+    for s, (H, W) in enumerate(sizes):
+        for t, x in enumerate(frames[s]):
+            b = alone.encode(x[None])[0]
+            o = torch.empty((1, 3, H, W), device="cuda")
+            alone.decode([b], o)
+            ref_bits[(s, t)], ref_img[(s, t)] = b, o[0]
+    sids = [srv.open_stream(H, W) for H, W in sizes]
+    for rep in range(2):
+        outs, tick = {}, {}
+        for t in range(nf):
+            for s, sid in enumerate(sids):
+                buf = np.zeros(srv.max_stream_bytes(*sizes[s]), np.uint8)
+                outs[(s, t)] = buf
+                tick[srv.submit_encode(sid, frames[s][t], buf)] = (s, t)
+        bits = {}
+        for r in _drain(srv, len(tick), timeout_s=120.0):
+            assert r["status"] == 0 and r["direction"] == 0
+            key = tick[r["ticket"]]
+            bits[key] = outs[key][:r["bytes"]].tobytes()
+            assert bits[key] == ref_bits[key], f"encode {key} differs from the frame coded alone (round {rep})"
+        imgs, dtick, keep = {}, {}, []
+        for key, b in bits.items():
+            s, t = key
+            H, W = sizes[s]
+            keep.append(np.frombuffer(b, np.uint8).copy())
+            imgs[key] = torch.empty((3, H, W), device="cuda")
+            dtick[srv.submit_decode(sids[s], keep[-1], imgs[key])] = key
+        for r in _drain(srv, len(dtick), timeout_s=120.0):
+            assert r["status"] == 0 and r["direction"] == 1
+            key = dtick[r["ticket"]]
+            assert torch.equal(imgs[key], ref_img[key]), f"decode {key} differs from the frame alone (round {rep})"
+    for sid in sids:
+        srv.close_stream(sid)
+    srv.close()
+    alone.close()
