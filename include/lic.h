@@ -61,9 +61,11 @@ typedef struct {
     int32_t  precision;        /* LIC_PREC_FP32, _BF16 or _FP8: g_a / g_s GEMM       */
                                /* operands and their activations in bf16, or in OCP  */
                                /* e4m3 with per-output-channel FP32 weight scales    */
-                               /* and a fixed activation scale (FP32 accumulation,   */
-                               /* FP32 GDN/IGDN); h_a, h_s, the quantisers and the   */
-                               /* scale index stay FP32                              */
+                               /* and a fixed activation scale (FP32 accumulation;   */
+                               /* GDN/IGDN normaliser from three bf16 part products, */
+                               /* about 2^-16 relative, normalisation in FP32);      */
+                               /* h_a, h_s, the quantisers and the scale index stay  */
+                               /* FP32                                               */
     int32_t  hs_out;           /* output activation of h_s: LIC_HS_EXP or _RELU      */
     int32_t  gs_mode;          /* 0: full synthesis transform g_s; 1: distilled g_s  */
                                /* (codec_load_distilled); 2: distilled g_s with a    */
