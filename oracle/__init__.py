@@ -29,6 +29,7 @@ import math
 import os
 import struct
 import subprocess
+import time
 
 import numpy as np
 
@@ -80,6 +81,8 @@ def lib():
         L.or_adamw.argtypes = [P, P, P, P, l, l, d, d, d, d, d]
         L.or_gdn.restype = None
         L.or_gdn.argtypes = [P, i, l, P, P, i, P]
+        L.or_gdn1.restype = None
+        L.or_gdn1.argtypes = [P, i, l, P, P, i, P]
         L.or_density_logit.restype = d
         L.or_density_logit.argtypes = [P, d]
         L.or_density_cdf.restype = d
@@ -193,6 +196,22 @@ def gdn(x, beta, gamma, inverse: bool = False) -> np.ndarray:
     out = np.empty_like(x)
     lib().or_gdn(_p(x), C, HW, _p(_f64(beta)), _p(_f64(gamma)), int(inverse), _p(out))
     return out
+
+
+def gdn1(x, beta, gamma, inverse: bool = False) -> np.ndarray:
+    """1DN (implementation C of Section IV.C; the paper gives no formula):
+    y_i = x_i / (beta_i + sum_j gamma_ij |x_j|); the inverse multiplies."""
+    x = _f64(x)
+    C = x.shape[0]
+    HW = int(np.prod(x.shape[1:]))
+    out = np.empty_like(x)
+    lib().or_gdn1(_p(x), C, HW, _p(_f64(beta)), _p(_f64(gamma)), int(inverse), _p(out))
+    return out
+
+
+def norm(x, beta, gamma, inverse: bool, kind: int) -> np.ndarray:
+    """The transforms' normalisation: GDN / IGDN (kind 0) or 1DN (kind 1)."""
+    return gdn1(x, beta, gamma, inverse) if kind == 1 else gdn(x, beta, gamma, inverse)
 
 
 def relu(x):
@@ -342,12 +361,13 @@ class Model:
     """Parameters of one codec plus the entropy tables derived from them.
 
     kind 0 = factorized prior, 1 = scale hyperprior.  hs_out selects the
-    output activation of h_s (1 = exp, 0 = ReLU).
+    output activation of h_s (1 = exp, 0 = ReLU); norm the normalisation of
+    g_a / g_s (0 = GDN / IGDN, 1 = 1DN and its inverse).
     """
 
-    def __init__(self, params, kind: int, N: int, M: int, blob: bytes = b"", hs_out: int = 1):
+    def __init__(self, params, kind: int, N: int, M: int, blob: bytes = b"", hs_out: int = 1, norm: int = 0):
         self.P = {k: np.asarray(v) for k, v in params.items()}
-        self.kind, self.N, self.M, self.hs_out = kind, N, M, hs_out
+        self.kind, self.N, self.M, self.hs_out, self.norm = kind, N, M, hs_out, norm
         self.model_id = fnv1a32(blob) if blob else 0
         dens = self.P["eb.density"]
         # channel offsets: FP64 bisection, rounded to float32
@@ -365,7 +385,7 @@ class Model:
         for i in range(4):
             h = conv2d(h, P[f"ga{i}.w"], P[f"ga{i}.b"], 2, 2)
             if i < 3:
-                h = gdn(h, P[f"ga{i}.beta"], P[f"ga{i}.gamma"])
+                h = norm(h, P[f"ga{i}.beta"], P[f"ga{i}.gamma"], False, self.norm)
             if keep is not None:
                 keep.append(h)
         return h
@@ -376,7 +396,7 @@ class Model:
         for i in range(4):
             h = deconv2d(h, P[f"gs{i}.w"], P[f"gs{i}.b"], 2, 2, 1)
             if i < 3:
-                h = gdn(h, P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
+                h = norm(h, P[f"gs{i}.beta"], P[f"gs{i}.gamma"], True, self.norm)
             if keep is not None:
                 keep.append(h)
         return h
@@ -414,47 +434,56 @@ class Model:
         return hwc.ravel() - SYM_MIN, np.ascontiguousarray(tab).ravel()
 
     # ---- codec ----
-    def encode(self, x, S: int = 1):
-        """x: 3 x H x W in [0,1].  Returns (bitstream bytes, intermediates)."""
+    def encode(self, x, S: int = 1, times=None):
+        """x: 3 x H x W in [0,1].  Returns (bitstream bytes, intermediates).
+        times: optional dict that receives the wall seconds of each stage."""
+        T = _Stages(times)
         _, H, W = x.shape
         xp = pad64(np.asarray(x, np.float64))
         inter = {"ga": []}
-        y = self.g_a(xp, inter["ga"])
+        with T("g_a"):
+            y = self.g_a(xp, inter["ga"])
         inter["y"] = y
         M, Hy, Wy = y.shape
         payloads = []
         if self.kind == 0:
             sym_y, yhat = quantize(y, self.medians[:, None, None])
             inter["sym_y"] = sym_y
-            syms, tabs = self._code_factorized(sym_y)
-            syms = syms.reshape(Hy, Wy * M)
-            tabs = tabs.reshape(Hy, Wy * M)
-            ys = [rans_encode(syms[a:b], tabs[a:b], self.freq_fact) for a, b in self.slice_rows(Hy, S)]
+            with T("rans_y"):
+                syms, tabs = self._code_factorized(sym_y)
+                syms = syms.reshape(Hy, Wy * M)
+                tabs = tabs.reshape(Hy, Wy * M)
+                ys = [rans_encode(syms[a:b], tabs[a:b], self.freq_fact) for a, b in self.slice_rows(Hy, S)]
         else:
             inter["ha"] = []
-            z = self.h_a(y, inter["ha"])
+            with T("h_a"):
+                z = self.h_a(y, inter["ha"])
             inter["z"] = z
             sym_z, zhat = quantize(z, self.medians[:, None, None])
             inter["sym_z"] = sym_z
-            v = self.h_s(zhat, inter.setdefault("hs", []))
+            with T("h_s"):
+                v = self.h_s(zhat, inter.setdefault("hs", []))
             inter["v"] = v
             idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
             inter["idx"] = idx
             sym_y, yhat = quantize(y, 0.0)
             inter["sym_y"] = sym_y
-            zs, zt = self._code_factorized(sym_z)
-            payloads.append(rans_encode(zs, zt, self.freq_fact))
-            ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
-            ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
-            ys = [rans_encode(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+            with T("rans_z"):
+                zs, zt = self._code_factorized(sym_z)
+                payloads.append(rans_encode(zs, zt, self.freq_fact))
+            with T("rans_y"):
+                ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
+                ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
+                ys = [rans_encode(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
         inter["yhat"] = yhat
         bits = pack_container(self.kind, self.hs_out, S, H, W, self.N, self.M, self.model_id,
-                              payloads[0] if self.kind == 1 else None, ys)
+                              payloads[0] if self.kind == 1 else None, ys, norm=self.norm)
         return bits, inter
 
-    def decode(self, bits: bytes, keep=None):
+    def decode(self, bits: bytes, keep=None, times=None):
+        T = _Stages(times)
         hdr = parse_container(bits)
-        if hdr["model_id"] != self.model_id or hdr["kind"] != self.kind:
+        if hdr["model_id"] != self.model_id or hdr["kind"] != self.kind or hdr["norm"] != self.norm:
             raise ValueError("bitstream was made by another model")
         H, W, S = hdr["H"], hdr["W"], hdr["S"]
         Hy, Wy = 4 * math.ceil(H / 64), 4 * math.ceil(W / 64)
@@ -462,29 +491,52 @@ class Model:
         inter = {} if keep is None else keep
         if self.kind == 0:
             yhat_hwc = np.empty((Hy, Wy, M), np.float64)
-            for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
-                tab = np.broadcast_to(np.arange(M, dtype=np.int32), (b - a, Wy, M))
-                sym = rans_decode(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
-                yhat_hwc[a:b] = sym + SYM_MIN + self.medians[None, None, :].astype(np.float64)
+            with T("rans_y"):
+                for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
+                    tab = np.broadcast_to(np.arange(M, dtype=np.int32), (b - a, Wy, M))
+                    sym = rans_decode(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
+                    yhat_hwc[a:b] = sym + SYM_MIN + self.medians[None, None, :].astype(np.float64)
         else:
             Hz, Wz = Hy // 4, Wy // 4
-            tab = np.broadcast_to(np.arange(N, dtype=np.int32), (Hz, Wz, N))
-            sz = rans_decode(hdr["z"], tab, self.freq_fact, Hz * Wz * N).reshape(Hz, Wz, N) + SYM_MIN
+            with T("rans_z"):
+                tab = np.broadcast_to(np.arange(N, dtype=np.int32), (Hz, Wz, N))
+                sz = rans_decode(hdr["z"], tab, self.freq_fact, Hz * Wz * N).reshape(Hz, Wz, N) + SYM_MIN
             zhat = np.transpose(sz, (2, 0, 1)) + self.medians[:, None, None].astype(np.float64)
             inter["sym_z"] = np.transpose(sz, (2, 0, 1))
-            v = self.h_s(zhat)
+            with T("h_s"):
+                v = self.h_s(zhat)
             idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
             inter["idx"] = idx
             idx_hwc = np.transpose(idx, (1, 2, 0))
             yhat_hwc = np.empty((Hy, Wy, M), np.float64)
-            for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
-                sym = rans_decode(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
-                yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
+            with T("rans_y"):
+                for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
+                    sym = rans_decode(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
+                    yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
         yhat = np.transpose(yhat_hwc, (2, 0, 1))
         inter["yhat"] = yhat
-        xr = self.g_s(yhat)
+        with T("g_s"):
+            xr = self.g_s(yhat)
         inter["x_pre"] = xr
         return np.clip(xr, 0.0, 1.0)[:, :H, :W], inter
+
+
+class _Stages:
+    """Accumulates the wall time of named stages into a dict (or does nothing)."""
+
+    def __init__(self, times):
+        self.times = times
+
+    def __call__(self, name):
+        self.name = name
+        return self
+
+    def __enter__(self):
+        self.t0 = time.perf_counter()
+
+    def __exit__(self, *exc):
+        if self.times is not None:
+            self.times[self.name] = self.times.get(self.name, 0.0) + time.perf_counter() - self.t0
 
 
 # ----------------------------------------------------------------------------
@@ -492,9 +544,10 @@ class Model:
 # output of h_s), u8 S, u16 H, u16 W, u16 N, u16 M, u32 model id,
 # [u32 len_z], S x u32 len_y, payloads z, y_0 .. y_{S-1}; little-endian.
 # ----------------------------------------------------------------------------
-def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys) -> bytes:
+def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys, norm: int = 0) -> bytes:
+    """flags: bit 0 = exp output of h_s, bit 1 = 1DN instead of GDN."""
     out = bytearray(b"LICS")
-    out += struct.pack("<BBBBHHHHI", 1, kind, hs_out & 1, S, H, W, N, M, model_id)
+    out += struct.pack("<BBBBHHHHI", 1, kind, (hs_out & 1) | ((norm & 1) << 1), S, H, W, N, M, model_id)
     if kind == 1:
         out += struct.pack("<I", len(z))
     out += struct.pack(f"<{S}I", *[len(y) for y in ys])
@@ -519,7 +572,8 @@ def parse_container(bits: bytes) -> dict:
     pos += 4 * nlen
     if pos + sum(lens) != len(bits):
         raise ValueError("length mismatch")
-    hdr = {"kind": kind, "hs_out": flags & 1, "S": S, "H": H, "W": W, "N": N, "M": M, "model_id": mid}
+    hdr = {"kind": kind, "hs_out": flags & 1, "norm": (flags >> 1) & 1, "S": S, "H": H, "W": W, "N": N, "M": M,
+           "model_id": mid}
     if kind == 1:
         hdr["z"] = bits[pos:pos + lens[0]]
         pos += lens[0]

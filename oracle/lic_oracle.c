@@ -13,7 +13,9 @@
  *     factorized-prior and scale-hyperprior codecs (Section III.A-B, Fig. 1).
  *   - GDN / IGDN, the normalisation the paper names as the main overhead of
  *     those transforms (Section IV.C): y_i = x_i / sqrt(beta_i + sum_j
- *     gamma_ij x_j^2), and x_i * sqrt(...) for the inverse.
+ *     gamma_ij x_j^2), and x_i * sqrt(...) for the inverse; and 1DN, the
+ *     cheaper normalisation of implementation C (same section), read as
+ *     y_i = x_i / (beta_i + sum_j gamma_ij |x_j|) and x_i * (...).
  *   - the per-channel factorized density (entropy bottleneck of the
  *     factorized prior, Section III.A), its median, and the integer
  *     frequency tables with 16-bit precision.
@@ -190,6 +192,27 @@ void or_gdn(const double* x, int C, long HW, const double* beta, const double* g
             }
             double xi = x[(long)i * HW + q];
             out[(long)i * HW + q] = inverse ? xi * sqrt(n) : xi / sqrt(n);
+        }
+}
+
+/* ------------------------------------------------------------------------ */
+/* 1DN, the cheaper normalisation that replaces GDN in the paper's          */
+/* implementation C (Section IV.C; the paper names it and cites it but      */
+/* prints no formula).  Read as GDN with the square of the channel mixing   */
+/* replaced by the absolute value and no square root:                       */
+/*   n_i = beta_i + sum_j gamma[i][j] |x_j|                                 */
+/*   forward: x_i / n_i      inverse: x_i * n_i                             */
+/* ------------------------------------------------------------------------ */
+void or_gdn1(const double* x, int C, long HW, const double* beta, const double* gamma,
+             int inverse, double* out)
+{
+#pragma omp parallel for schedule(static)
+    for (long q = 0; q < HW; ++q)
+        for (int i = 0; i < C; ++i) {
+            double n = beta[i];
+            for (int j = 0; j < C; ++j) n += gamma[(long)i * C + j] * fabs(x[(long)j * HW + q]);
+            double xi = x[(long)i * HW + q];
+            out[(long)i * HW + q] = inverse ? xi * n : xi / n;
         }
 }
 
