@@ -103,6 +103,10 @@ def lib():
         L.or_rans_encode.argtypes = [P, P, l, P, P, l]
         L.or_rans_decode.restype = i
         L.or_rans_decode.argtypes = [P, l, P, l, P, P]
+        L.or_rans_ileave_encode.restype = l
+        L.or_rans_ileave_encode.argtypes = [P, P, l, i, P, P, l]
+        L.or_rans_ileave_decode.restype = i
+        L.or_rans_ileave_decode.argtypes = [P, l, P, l, i, P, P]
         _lib = L
     return _lib
 
@@ -332,6 +336,34 @@ def rans_decode(data: bytes, tab, freq, n: int) -> np.ndarray:
     buf = np.frombuffer(data, np.uint8).copy() if len(data) else np.zeros(1, np.uint8)
     sym = np.empty(n, np.int32)
     rc = lib().or_rans_decode(_p(buf), len(data), _p(tab), n, _p(freq), _p(sym))
+    if rc != 0:
+        raise ValueError("corrupt rANS stream (code %d)" % rc)
+    return sym
+
+
+RANS_LANES = 8       # states of the interleaved coder
+
+
+def rans_ileave_encode(sym, tab, freq, K: int = RANS_LANES) -> bytes:
+    """Interleaved word-wise rANS with K states (symbol i on state i mod K)."""
+    sym = np.ascontiguousarray(sym, np.int32).ravel()
+    tab = np.ascontiguousarray(tab, np.int32).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    n = sym.size
+    cap = 4 * n + 4 * K + 64
+    out = np.empty(cap, np.uint8)
+    ln = lib().or_rans_ileave_encode(_p(sym), _p(tab), n, K, _p(freq), _p(out), cap)
+    if ln < 0:
+        raise RuntimeError("rANS output overflow")
+    return out[:ln].tobytes()
+
+
+def rans_ileave_decode(data: bytes, tab, freq, n: int, K: int = RANS_LANES) -> np.ndarray:
+    tab = np.ascontiguousarray(tab, np.int32).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    buf = np.frombuffer(data, np.uint8).copy() if len(data) else np.zeros(1, np.uint8)
+    sym = np.empty(n, np.int32)
+    rc = lib().or_rans_ileave_decode(_p(buf), len(data), _p(tab), n, K, _p(freq), _p(sym))
     if rc != 0:
         raise ValueError("corrupt rANS stream (code %d)" % rc)
     return sym

@@ -400,3 +400,89 @@ int or_rans_decode(const uint8_t* in, long len, const int32_t* tab, long n,
     if (x != OR_RANS_L || pos != len) return -2;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Interleaved word-wise rANS (the faster entropy coding the paper points   */
+/* to in Sections II and VII; the construction is Giesen's interleaved      */
+/* rANS, 2014).  K coder states share one stream.  Each state is 32 bits    */
+/* with lower bound L = 2^16 and exchanges 16-bit words with the stream;    */
+/* frequencies have 16-bit precision, as above.  Symbol i is coded by state */
+/* i mod K.  Encoding runs over the symbols in reverse: before symbol i its */
+/* state x pushes its low 16 bits and shifts right by 16 if x >= f 2^16,     */
+/* then x <- (x / f) 2^16 + x mod f + start.  The stream is the K final     */
+/* states (u32 little-endian, state 0 first) followed by the pushed words   */
+/* in the reverse of their push order (u16 little-endian).  Decoding runs   */
+/* forward: slot = x mod 2^16, the symbol a with start_a <= slot <          */
+/* start_a + f_a, x <- f_a (x / 2^16) + slot - start_a, then one word is    */
+/* read, x <- x 2^16 + word, if x < 2^16.  Because every state reads its    */
+/* words in the reverse of the order the encoder pushed them, the one       */
+/* shared stream serves all K states.  At the end every state is L again    */
+/* and every word has been read.                                            */
+/* Returns the stream length in bytes, or -1 if it does not fit in cap.     */
+/* ------------------------------------------------------------------------ */
+#define OR_RANS16_L (1u << 16)
+
+long or_rans_ileave_encode(const int32_t* sym, const int32_t* tab, long n, int K,
+                           const uint32_t* freq, uint8_t* out, long cap)
+{
+    uint32_t x[64];
+    if (K < 1 || K > 64) return -1;
+    for (int j = 0; j < K; ++j) x[j] = OR_RANS16_L;
+    long pos = cap;
+    for (long i = n - 1; i >= 0; --i) {
+        const int j = (int)(i % K);
+        const uint32_t* f = freq + (long)tab[i] * OR_NSYM;
+        uint32_t fs = f[sym[i]];
+        uint32_t st = cum_start(f, sym[i]);
+        if (x[j] >= (fs << 16)) {
+            if (pos < 2) return -1;
+            pos -= 2;
+            out[pos + 0] = (uint8_t)(x[j]);
+            out[pos + 1] = (uint8_t)(x[j] >> 8);
+            x[j] >>= 16;
+        }
+        x[j] = ((x[j] / fs) << OR_PREC) + (x[j] % fs) + st;
+    }
+    if (pos < 4L * K) return -1;
+    pos -= 4L * K;
+    for (int j = 0; j < K; ++j) {
+        out[pos + 4 * j + 0] = (uint8_t)(x[j]);
+        out[pos + 4 * j + 1] = (uint8_t)(x[j] >> 8);
+        out[pos + 4 * j + 2] = (uint8_t)(x[j] >> 16);
+        out[pos + 4 * j + 3] = (uint8_t)(x[j] >> 24);
+    }
+    long len = cap - pos;
+    memmove(out, out + pos, (size_t)len);
+    return len;
+}
+
+/* Returns 0 on success, -1 if the stream is truncated, -2 if it does not   */
+/* end with every state at L and every word read.                           */
+int or_rans_ileave_decode(const uint8_t* in, long len, const int32_t* tab, long n, int K,
+                          const uint32_t* freq, int32_t* sym)
+{
+    uint32_t x[64];
+    if (K < 1 || K > 64 || len < 4L * K) return -1;
+    for (int j = 0; j < K; ++j)
+        x[j] = (uint32_t)in[4 * j] | ((uint32_t)in[4 * j + 1] << 8) | ((uint32_t)in[4 * j + 2] << 16) |
+               ((uint32_t)in[4 * j + 3] << 24);
+    long pos = 4L * K;
+    for (long i = 0; i < n; ++i) {
+        const int j = (int)(i % K);
+        const uint32_t* f = freq + (long)tab[i] * OR_NSYM;
+        uint32_t slot = x[j] & ((1u << OR_PREC) - 1);
+        int a = 0;
+        uint32_t st = 0;
+        while (a < OR_NSYM - 1 && st + f[a] <= slot) { st += f[a]; ++a; }
+        sym[i] = a;
+        x[j] = f[a] * (x[j] >> OR_PREC) + slot - st;
+        if (x[j] < OR_RANS16_L) {
+            if (pos + 2 > len) return -1;
+            x[j] = (x[j] << 16) | (uint32_t)in[pos] | ((uint32_t)in[pos + 1] << 8);
+            pos += 2;
+        }
+    }
+    for (int j = 0; j < K; ++j)
+        if (x[j] != OR_RANS16_L) return -2;
+    return pos == len ? 0 : -2;
+}
