@@ -289,6 +289,20 @@ const char* lic_distill_last_error(const lic_distill_t* d);
  * handle's stream and waits for it. */
 int lic_distill_forward(lic_distill_t* d, const int8_t* sym, const float* mu, int n, int hy, int wy,
                         float* pre, float* x_hat, int H, int W);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * forward pass as lic_distill_forward, with the two hidden activations in a
+ * fixed workspace of 32 MiB that the library holds per device instead of the
+ * handle's buffers.  The call allocates nothing (the first call on a device
+ * looks the workspace up once).  Needs 80 * n * hy * wy * F bytes with FP32
+ * operands, 40 * n * hy * wy * F with bf16 (plus up to 255 of alignment):
+ * LIC_E_BUDGET beyond the 32 MiB (one 720p frame, hy 48 x wy 80, F 64,
+ * fits in either precision).  Every
+ * call on one device shares that workspace, so calls that overlap on one
+ * GPU (several threads or handles) race; nothing in it needs to start at
+ * zero.  Runs on the handle's stream and waits for it. */
+int lic_distill_forward_noalloc(lic_distill_t* d, const int8_t* sym, const float* mu, int n, int hy, int wy,
+                                float* pre, float* x_hat, int H, int W);
 /* Loss (mean squared error of the unclamped output against target, NCHW
  * [n][3][16 hy][16 wy]) and its gradient w.r.t. every parameter, without an
  * update.  grads: host array of param_count floats, or NULL; loss: host. */

@@ -106,6 +106,7 @@ SIGNATURES = {
     "lic_distill_destroy": (None, [P]),
     "lic_distill_last_error": (ctypes.c_char_p, [P]),
     "lic_distill_forward": (c_int, [P, P, P, c_int, c_int, c_int, P, P, c_int, c_int]),
+    "lic_distill_forward_noalloc": (c_int, [P, P, P, c_int, c_int, c_int, P, P, c_int, c_int]),
     "lic_distill_grads": (c_int, [P, P, P, P, c_int, c_int, c_int, P, P]),
     "lic_distill_step": (c_int, [P, P, P, P, c_long, P, c_int, c_int, c_int, P]),
     "lic_distill_sync": (c_int, [P]),

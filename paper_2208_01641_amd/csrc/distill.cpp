@@ -180,11 +180,22 @@ int DistillNet::check_dims(int n, int hy, int wy)
     return LIC_OK;
 }
 
+size_t DistillNet::hidden_bytes(int n, int hy, int wy, size_t* h2_off) const
+{
+    const size_t act = cfg.precision == LIC_PREC_BF16 ? 2 : 4;
+    const size_t px = (size_t)n * hy * wy * F * act;
+    const size_t b1 = (4 * px + 255) / 256 * 256;
+    if (h2_off) *h2_off = b1;
+    return b1 + 16 * px;
+}
+
 int DistillNet::forward(const int8_t* sym, const float* mu, int n, int hy, int wy, float* pre, float* x_hat, int H,
-                        int W, hipStream_t s)
+                        int W, hipStream_t s, void* h1, void* h2)
 {
     int rc = check_dims(n, hy, wy);
     if (rc != LIC_OK) return rc;
+    if (!h1) h1 = d_h1;
+    if (!h2) h2 = d_h2;
     if (x_hat && (H < 1 || W < 1 || H > 16 * hy || W > 16 * wy)) { err = "crop larger than the decoded grid"; return LIC_E_ARG; }
     auto base = [&](const Layer& L, const void* in, void* out, void* aux, int Hin, int Win, int s_out, int Hout,
                     int Wout) {
@@ -212,9 +223,9 @@ int DistillNet::forward(const int8_t* sym, const float* mu, int n, int hy, int w
         a.pad = L.p;
         return a;
     };
-    ConvArgs a1 = base(fwd[0], sym, d_h1, nullptr, hy, wy, 2, 2 * hy, 2 * wy);
-    ConvArgs a2 = base(fwd[1], d_h1, d_h2, nullptr, 2 * hy, 2 * wy, 2, 4 * hy, 4 * wy);
-    ConvArgs a3 = base(fwd[2], d_h2, x_hat, pre, 4 * hy, 4 * wy, 4, 16 * hy, 16 * wy);
+    ConvArgs a1 = base(fwd[0], sym, h1, nullptr, hy, wy, 2, 2 * hy, 2 * wy);
+    ConvArgs a2 = base(fwd[1], h1, h2, nullptr, 2 * hy, 2 * wy, 2, 4 * hy, 4 * wy);
+    ConvArgs a3 = base(fwd[2], h2, x_hat, pre, 4 * hy, 4 * wy, 4, 16 * hy, 16 * wy);
     a3.Hc = H;
     a3.Wc = W;
     if ((rc = launch_conv_policy(fwd[0].shape, a1, (long)hy * wy, s, &err)) != LIC_OK) return rc;
@@ -385,6 +396,33 @@ int lic_distill_forward(lic_distill_t* d, const int8_t* sym, const float* mu, in
     if (!d || !sym || (!pre && !x_hat)) return LIC_E_ARG;
     if (hipSetDevice(d->cfg.hip_device) != hipSuccess) return LIC_E_HIP;
     const int rc = d->forward(sym, mu, n, hy, wy, pre, x_hat, H, W, d->stream);
+    if (rc != LIC_OK) return rc;
+    if (hipStreamSynchronize(d->stream) != hipSuccess) { d->err = "forward failed"; return LIC_E_HIP; }
+    return LIC_OK;
+}
+
+int lic_distill_forward_noalloc(lic_distill_t* d, const int8_t* sym, const float* mu, int n, int hy, int wy,
+                                float* pre, float* x_hat, int H, int W)
+{
+    if (!d || !sym || (!pre && !x_hat)) return LIC_E_ARG;
+    int rc = d->check_dims(n, hy, wy);
+    if (rc != LIC_OK) return rc;
+    if (hipSetDevice(d->cfg.hip_device) != hipSuccess) return LIC_E_HIP;
+    void* ws = nullptr;
+    size_t cap = 0;
+    const hipError_t e = lic::distill_scratch(&ws, &cap);
+    if (e != hipSuccess) {
+        d->err = std::string("workspace lookup failed: ") + hipGetErrorString(e);
+        return LIC_E_HIP;
+    }
+    size_t h2_off = 0;
+    const size_t need = d->hidden_bytes(n, hy, wy, &h2_off);
+    if (need > cap) {
+        d->err = "hidden activations need " + std::to_string(need) + " bytes; the fixed workspace holds " +
+                 std::to_string(cap);
+        return LIC_E_BUDGET;
+    }
+    rc = d->forward(sym, mu, n, hy, wy, pre, x_hat, H, W, d->stream, ws, static_cast<char*>(ws) + h2_off);
     if (rc != LIC_OK) return rc;
     if (hipStreamSynchronize(d->stream) != hipSuccess) { d->err = "forward failed"; return LIC_E_HIP; }
     return LIC_OK;

@@ -64,8 +64,12 @@ struct DistillNet {
     ~DistillNet();
     int create(const lic_distill_config& c, const float* params, size_t n);
     // Launches the forward pass on stream s (no wait); pre / x_hat as in lic.h.
+    // h1 / h2: the hidden activations (null: the handle's own buffers).
     int forward(const int8_t* sym, const float* mu, int n, int hy, int wy, float* pre, float* x_hat, int H, int W,
-                hipStream_t s);
+                hipStream_t s, void* h1 = nullptr, void* h2 = nullptr);
+    // Bytes of the two hidden activations of an n x hy x wy call, the second
+    // starting at *h2_off (256-byte aligned).
+    size_t hidden_bytes(int n, int hy, int wy, size_t* h2_off) const;
     // Loss and gradients into d_grad (stream, no wait); loss to loss_dev.
     int backward(const int8_t* sym, const float* mu, const float* target, int n, int hy, int wy, float* loss_dev);
     int update();                        // AdamW step and repack

@@ -44,6 +44,10 @@ struct AdamCoef {
 hipError_t launch_adamw(float* w, float* m, float* v, const float* g, long n, const AdamCoef& k, hipStream_t s);
 hipError_t launch_gather_pack(const float* master, const int32_t* idx, long n, float* out32, void* out16,
                               hipStream_t s);
+// Device address and size of the fixed workspace of the allocation-free
+// forward pass, on the current device (looked up once per device).
+constexpr size_t kDistillScratchBytes = size_t(32) << 20;
+hipError_t distill_scratch(void** ptr, size_t* bytes);
 // *out = sum of (a - b)^2 over n elements
 hipError_t launch_sqdiff(const float* a, const float* b, long n, int chunk, float* part, float* out, hipStream_t s);
 

@@ -8,10 +8,39 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "distill_kernels.h"
 
 namespace lic {
+
+// Workspace of the allocation-free forward pass: the two hidden activations
+// of one call.  Every device that runs that pass holds its own copy of this
+// array until the process ends; host code reaches it only through the
+// address that hipGetSymbolAddress returns on that device.
+static __device__ __align__(256) unsigned char scratch[kDistillScratchBytes];
+
+hipError_t distill_scratch(void** ptr, size_t* bytes)
+{
+    constexpr int kMaxDevices = 64;
+    static std::mutex m;
+    static void* addr[kMaxDevices] = {};
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> g(m);
+    if (!addr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    *bytes = kDistillScratchBytes;
+    return hipSuccess;
+}
 
 typedef float f4 __attribute__((ext_vector_type(4)));
 

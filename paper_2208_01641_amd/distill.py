@@ -91,6 +91,16 @@ class Distill:
                                             None if pre is None else _ptr(pre),
                                             None if x_hat is None else _ptr(x_hat), H, W))
 
+    def forward_noalloc(self, sym, mu=None, pre=None, x_hat=None, H: int = 0, W: int = 0):
+        """forward() with the hidden activations in the library's fixed
+        per-device workspace (the call allocates no device memory)."""
+        n, hy, wy, _ = sym.shape
+        if x_hat is not None and not H:
+            H, W = x_hat.shape[2], x_hat.shape[3]
+        self._check(lib.lic_distill_forward_noalloc(self._h, _ptr(sym), self._mu(mu), n, hy, wy,
+                                                    None if pre is None else _ptr(pre),
+                                                    None if x_hat is None else _ptr(x_hat), H, W))
+
     def grads(self, sym, target, mu=None):
         """Loss and parameter gradients (flat float32 vector) without an update."""
         n, hy, wy, _ = sym.shape
