@@ -52,6 +52,7 @@ typedef enum {
 enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1 };
 enum { LIC_PREC_FP32 = 0, LIC_PREC_BF16 = 1, LIC_PREC_FP8 = 2 };
 enum { LIC_HS_RELU = 0, LIC_HS_EXP = 1 };
+enum { LIC_NORM_GDN = 0, LIC_NORM_1DN = 1 };
 
 /* Creation parameters.  Fill with codec_default_config() first. */
 typedef struct {
@@ -82,10 +83,22 @@ typedef struct {
     int32_t  hip_device;       /* HIP device ordinal                                 */
     int32_t  use_graphs;       /* serving: run each GPU stage of a (frame size,      */
                                /* batch, slot) as a captured HIP graph               */
+    int32_t  norm;             /* normalisation of g_a / g_s (Section IV.C):         */
+                               /* LIC_NORM_GDN y_i = x_i / sqrt(beta_i + sum_j       */
+                               /* gamma_ij x_j^2), inverse x_i sqrt(...); or         */
+                               /* LIC_NORM_1DN (implementation C, whose formula the  */
+                               /* paper does not print; read as) y_i = x_i /         */
+                               /* (beta_i + sum_j gamma_ij |x_j|), inverse x_i (...) */
+                               /* with the same beta / gamma; recorded in streams    */
+    int32_t  rans_lanes;       /* entropy coder: 0 byte-wise rANS with one state;    */
+                               /* 2, 4, 8, 16 or 32: interleaved word-wise rANS with */
+                               /* that many states (lic_rans_ileave_encode); recorded */
+                               /* in streams                                         */
 } codec_config;
 
 /* Defaults: hyperprior, N=128, M=192, FP32, exp output, S=8, 8 entropy
- * threads, zero_copy=1, 6 tasks in flight, 1088x1920 max, batch 1, graphs on. */
+ * threads, zero_copy=1, 6 tasks in flight, 1088x1920 max, batch 1, graphs on,
+ * GDN, byte-wise rANS. */
 void codec_default_config(codec_config* cfg);
 
 /* Creates a codec from a "LICW" weight blob (see DESIGN notes: per-layer
@@ -339,6 +352,21 @@ long lic_rans_encode(const uint8_t* sym, const uint8_t* tab, long n,
  * end in the initial state with every byte consumed. */
 int  lic_rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n,
                      const uint32_t* freq, int ntab, uint8_t* sym);
+/* Interleaved word-wise rANS: the faster entropy coding the paper points to
+ * (Sections II and VII).  `lanes` = K coder states (2, 4, 8, 16 or 32) share
+ * one stream; symbol i is coded by state i mod K, so K independent chains
+ * run side by side in one thread.  States are 32 bits in [2^16, 2^32) and
+ * exchange 16-bit words with the stream; frequencies as above.  Stream: the
+ * K final states (u32 little-endian, state 0 first), then the words (u16
+ * little-endian) in the reverse of the order the encoder pushed them.  At
+ * most 2 n + 4 K bytes.  Returns the stream length, LIC_E_SMALLBUF, or
+ * LIC_E_ARG (bad lanes, symbol or table). */
+long lic_rans_ileave_encode(int lanes, const uint8_t* sym, const uint8_t* tab, long n,
+                            const uint32_t* freq, int ntab, uint8_t* out, size_t cap);
+/* LIC_OK, or LIC_E_CORRUPT if the stream is truncated or does not end with
+ * every state back at 2^16 and every word read. */
+int  lic_rans_ileave_decode(int lanes, const uint8_t* in, size_t len, const uint8_t* tab, long n,
+                            const uint32_t* freq, int ntab, uint8_t* sym);
 /* FNV-1a 32-bit hash (the model id carried in every bitstream). */
 uint32_t lic_fnv1a(const void* data, size_t len);
 /* Entropy tables a codec would build from this weight blob, computed on the

@@ -394,12 +394,15 @@ class Model:
 
     kind 0 = factorized prior, 1 = scale hyperprior.  hs_out selects the
     output activation of h_s (1 = exp, 0 = ReLU); norm the normalisation of
-    g_a / g_s (0 = GDN / IGDN, 1 = 1DN and its inverse).
+    g_a / g_s (0 = GDN / IGDN, 1 = 1DN and its inverse); lanes the entropy
+    coder (0 = byte-wise rANS, K = interleaved word-wise rANS with K states).
     """
 
-    def __init__(self, params, kind: int, N: int, M: int, blob: bytes = b"", hs_out: int = 1, norm: int = 0):
+    def __init__(self, params, kind: int, N: int, M: int, blob: bytes = b"", hs_out: int = 1, norm: int = 0,
+                 lanes: int = 0):
         self.P = {k: np.asarray(v) for k, v in params.items()}
         self.kind, self.N, self.M, self.hs_out, self.norm = kind, N, M, hs_out, norm
+        self.lanes = lanes
         self.model_id = fnv1a32(blob) if blob else 0
         dens = self.P["eb.density"]
         # channel offsets: FP64 bisection, rounded to float32
@@ -465,6 +468,16 @@ class Model:
         tab = np.broadcast_to(np.arange(C, dtype=np.int32), hwc.shape)
         return hwc.ravel() - SYM_MIN, np.ascontiguousarray(tab).ravel()
 
+    def _enc(self, sym, tab, freq):
+        if self.lanes:
+            return rans_ileave_encode(sym, tab, freq, K=self.lanes)
+        return rans_encode(sym, tab, freq)
+
+    def _dec(self, data, tab, freq, n):
+        if self.lanes:
+            return rans_ileave_decode(data, tab, freq, n, K=self.lanes)
+        return rans_decode(data, tab, freq, n)
+
     # ---- codec ----
     def encode(self, x, S: int = 1, times=None):
         """x: 3 x H x W in [0,1].  Returns (bitstream bytes, intermediates).
@@ -485,7 +498,7 @@ class Model:
                 syms, tabs = self._code_factorized(sym_y)
                 syms = syms.reshape(Hy, Wy * M)
                 tabs = tabs.reshape(Hy, Wy * M)
-                ys = [rans_encode(syms[a:b], tabs[a:b], self.freq_fact) for a, b in self.slice_rows(Hy, S)]
+                ys = [self._enc(syms[a:b], tabs[a:b], self.freq_fact) for a, b in self.slice_rows(Hy, S)]
         else:
             inter["ha"] = []
             with T("h_a"):
@@ -502,20 +515,21 @@ class Model:
             inter["sym_y"] = sym_y
             with T("rans_z"):
                 zs, zt = self._code_factorized(sym_z)
-                payloads.append(rans_encode(zs, zt, self.freq_fact))
+                payloads.append(self._enc(zs, zt, self.freq_fact))
             with T("rans_y"):
                 ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
                 ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
-                ys = [rans_encode(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+                ys = [self._enc(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
         inter["yhat"] = yhat
         bits = pack_container(self.kind, self.hs_out, S, H, W, self.N, self.M, self.model_id,
-                              payloads[0] if self.kind == 1 else None, ys, norm=self.norm)
+                              payloads[0] if self.kind == 1 else None, ys, norm=self.norm, lanes=self.lanes)
         return bits, inter
 
     def decode(self, bits: bytes, keep=None, times=None):
         T = _Stages(times)
         hdr = parse_container(bits)
-        if hdr["model_id"] != self.model_id or hdr["kind"] != self.kind or hdr["norm"] != self.norm:
+        if (hdr["model_id"] != self.model_id or hdr["kind"] != self.kind or hdr["norm"] != self.norm
+                or hdr["lanes"] != self.lanes):
             raise ValueError("bitstream was made by another model")
         H, W, S = hdr["H"], hdr["W"], hdr["S"]
         Hy, Wy = 4 * math.ceil(H / 64), 4 * math.ceil(W / 64)
@@ -526,13 +540,13 @@ class Model:
             with T("rans_y"):
                 for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
                     tab = np.broadcast_to(np.arange(M, dtype=np.int32), (b - a, Wy, M))
-                    sym = rans_decode(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
+                    sym = self._dec(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
                     yhat_hwc[a:b] = sym + SYM_MIN + self.medians[None, None, :].astype(np.float64)
         else:
             Hz, Wz = Hy // 4, Wy // 4
             with T("rans_z"):
                 tab = np.broadcast_to(np.arange(N, dtype=np.int32), (Hz, Wz, N))
-                sz = rans_decode(hdr["z"], tab, self.freq_fact, Hz * Wz * N).reshape(Hz, Wz, N) + SYM_MIN
+                sz = self._dec(hdr["z"], tab, self.freq_fact, Hz * Wz * N).reshape(Hz, Wz, N) + SYM_MIN
             zhat = np.transpose(sz, (2, 0, 1)) + self.medians[:, None, None].astype(np.float64)
             inter["sym_z"] = np.transpose(sz, (2, 0, 1))
             with T("h_s"):
@@ -543,7 +557,7 @@ class Model:
             yhat_hwc = np.empty((Hy, Wy, M), np.float64)
             with T("rans_y"):
                 for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
-                    sym = rans_decode(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
+                    sym = self._dec(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
                     yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
         yhat = np.transpose(yhat_hwc, (2, 0, 1))
         inter["yhat"] = yhat
@@ -573,13 +587,18 @@ class _Stages:
 
 # ----------------------------------------------------------------------------
 # bitstream container: "LICS", u8 version, u8 kind, u8 flags (bit 0 = exp
-# output of h_s), u8 S, u16 H, u16 W, u16 N, u16 M, u32 model id,
+# output of h_s, bit 1 = 1DN, bits 2..4 = log2 of the interleaved rANS
+# states, 0 for the byte-wise coder), u8 S, u16 H, u16 W, u16 N, u16 M, u32 model id,
 # [u32 len_z], S x u32 len_y, payloads z, y_0 .. y_{S-1}; little-endian.
 # ----------------------------------------------------------------------------
-def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys, norm: int = 0) -> bytes:
-    """flags: bit 0 = exp output of h_s, bit 1 = 1DN instead of GDN."""
+def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys, norm: int = 0, lanes: int = 0) -> bytes:
+    """flags: bit 0 = exp output of h_s, bit 1 = 1DN instead of GDN, bits 2..4
+    = log2(lanes) of the interleaved coder (0 = byte-wise rANS)."""
+    lg = 0 if lanes == 0 else int(lanes).bit_length() - 1
+    assert lanes == 0 or (lanes == 1 << lg and 1 <= lg <= 5)
     out = bytearray(b"LICS")
-    out += struct.pack("<BBBBHHHHI", 1, kind, (hs_out & 1) | ((norm & 1) << 1), S, H, W, N, M, model_id)
+    out += struct.pack("<BBBBHHHHI", 1, kind, (hs_out & 1) | ((norm & 1) << 1) | (lg << 2), S, H, W, N, M,
+                       model_id)
     if kind == 1:
         out += struct.pack("<I", len(z))
     out += struct.pack(f"<{S}I", *[len(y) for y in ys])
@@ -594,7 +613,7 @@ def parse_container(bits: bytes) -> dict:
     if len(bits) < 20 or bits[:4] != b"LICS":
         raise ValueError("not a LICS bitstream")
     ver, kind, flags, S, H, W, N, M, mid = struct.unpack_from("<BBBBHHHHI", bits, 4)
-    if ver != 1 or kind not in (0, 1) or S < 1 or H == 0 or W == 0:
+    if ver != 1 or kind not in (0, 1) or S < 1 or H == 0 or W == 0 or flags >> 5 or ((flags >> 2) & 7) > 5:
         raise ValueError("bad header")
     pos = 20
     nlen = S + (1 if kind == 1 else 0)
@@ -604,8 +623,9 @@ def parse_container(bits: bytes) -> dict:
     pos += 4 * nlen
     if pos + sum(lens) != len(bits):
         raise ValueError("length mismatch")
-    hdr = {"kind": kind, "hs_out": flags & 1, "norm": (flags >> 1) & 1, "S": S, "H": H, "W": W, "N": N, "M": M,
-           "model_id": mid}
+    lg = (flags >> 2) & 7
+    hdr = {"kind": kind, "hs_out": flags & 1, "norm": (flags >> 1) & 1, "lanes": (1 << lg) if lg else 0, "S": S,
+           "H": H, "W": W, "N": N, "M": M, "model_id": mid}
     if kind == 1:
         hdr["z"] = bits[pos:pos + lens[0]]
         pos += lens[0]

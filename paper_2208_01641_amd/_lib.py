@@ -38,6 +38,8 @@ class CodecConfig(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("hip_device", ctypes.c_int32),
         ("use_graphs", ctypes.c_int32),
+        ("norm", ctypes.c_int32),
+        ("rans_lanes", ctypes.c_int32),
     ]
 
 
@@ -92,6 +94,8 @@ SIGNATURES = {
     "codec_medians": (c_long, [P, P, c_size_t]),
     "lic_rans_encode": (c_long, [P, P, c_long, P, c_int, P, c_size_t]),
     "lic_rans_decode": (c_int, [P, c_size_t, P, c_long, P, c_int, P]),
+    "lic_rans_ileave_encode": (c_long, [c_int, P, P, c_long, P, c_int, P, c_size_t]),
+    "lic_rans_ileave_decode": (c_int, [c_int, P, c_size_t, P, c_long, P, c_int, P]),
     "lic_fnv1a": (c_uint32, [P, c_size_t]),
     "lic_blob_tables": (c_long, [P, c_size_t, c_int, P, c_size_t, P, c_size_t]),
     "codec_open_stream": (c_int, [P, c_int, c_int, P]),

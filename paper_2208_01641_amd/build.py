@@ -33,19 +33,34 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
+def _stale(obj: str, src: str) -> bool:
+    """An object is stale if it is missing or older than its source or any
+    header the sources include (csrc/*.h, include/*.h)."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    hdrs = [os.path.join(SRC, h) for h in os.listdir(SRC) if h.endswith(".h")]
+    inc = os.path.join(os.path.dirname(HERE), "include")
+    hdrs += [os.path.join(inc, h) for h in os.listdir(inc) if h.endswith(".h")]
+    return any(os.path.getmtime(p) >= t for p in [src] + hdrs)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compiles every source (incremental=True: only stale objects) and links."""
     os.makedirs(OUT, exist_ok=True)
     jobs = []
     objs = []
     for f in HIP_SOURCES:
         o = os.path.join(OUT, f + ".o")
-        jobs.append(HIPCC + ["-c", os.path.join(SRC, f), "-o", o])
+        if not incremental or _stale(o, os.path.join(SRC, f)):
+            jobs.append(HIPCC + ["-c", os.path.join(SRC, f), "-o", o])
         objs.append(o)
     for f in CPP_SOURCES:
         o = os.path.join(OUT, f + ".o")
-        jobs.append(CXX + ["-c", os.path.join(SRC, f), "-o", o])
+        if not incremental or _stale(o, os.path.join(SRC, f)):
+            jobs.append(CXX + ["-c", os.path.join(SRC, f), "-o", o])
         objs.append(o)
-    with ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+    with ThreadPoolExecutor(max_workers=max(1, min(8, len(jobs)))) as ex:
         for out in ex.map(_run, jobs):
             if verbose and out.strip():
                 print(out)
@@ -56,4 +71,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

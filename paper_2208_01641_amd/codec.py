@@ -39,14 +39,14 @@ class Codec:
     def __init__(self, blob: bytes, kind: int = 1, N: int = 128, M: int = 192, hs_out: int = 1, precision: int = 0,
                  y_slices: int = 8, entropy_threads: int = 8, zero_copy: int = 1, max_in_flight: int = 6,
                  max_h: int = 1088, max_w: int = 1920, max_batch: int = 1, hbm_budget_bytes: int = 0,
-                 device: int = 0, use_graphs: int = 1, gs_mode: int = 0):
+                 device: int = 0, use_graphs: int = 1, gs_mode: int = 0, norm: int = 0, rans_lanes: int = 0):
         cfg = _lib.CodecConfig()
         lib.codec_default_config(ctypes.byref(cfg))
         cfg.kind, cfg.N, cfg.M, cfg.hs_out, cfg.precision = kind, N, M, hs_out, precision
         cfg.y_slices, cfg.entropy_threads, cfg.zero_copy = y_slices, entropy_threads, zero_copy
         cfg.max_in_flight, cfg.max_h, cfg.max_w, cfg.max_batch = max_in_flight, max_h, max_w, max_batch
         cfg.hbm_budget_bytes, cfg.hip_device, cfg.use_graphs = hbm_budget_bytes, device, use_graphs
-        cfg.gs_mode = gs_mode
+        cfg.gs_mode, cfg.norm, cfg.rans_lanes = gs_mode, norm, rans_lanes
         self.cfg = cfg
         self.kind, self.N, self.M, self.S, self.precision = kind, N, M, y_slices, precision
         self._blob = ctypes.create_string_buffer(bytes(blob), len(blob))
@@ -80,7 +80,7 @@ class Codec:
         Hp, Wp = 64 * -(-H // 64), 64 * -(-W // 64)
         ny = (Hp // 16) * (Wp // 16) * self.M
         nz = (Hp // 64) * (Wp // 64) * self.N if self.kind == 1 else 0
-        return 20 + 4 * (self.S + 1) + 2 * (ny + nz) + 16 * 65
+        return 20 + 4 * (self.S + 1) + 2 * (ny + nz) + 160 * 65
 
     # ------------------------------------------------------------------
     def encode(self, x) -> list:
@@ -241,6 +241,31 @@ def rans_decode(data: bytes, tab, freq, n: int) -> np.ndarray:
     if rc != 0:
         raise LicError(rc, "lic_rans_decode")
     return sym
+
+
+def rans_ileave_encode(sym, tab, freq, lanes: int = 8) -> bytes:
+    sym = np.ascontiguousarray(sym, np.uint8).ravel()
+    tab = np.ascontiguousarray(tab, np.uint8).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    cap = 2 * sym.size + 4 * lanes + 64
+    out = np.empty(cap, np.uint8)
+    n = lib.lic_rans_ileave_encode(lanes, sym.ctypes.data, tab.ctypes.data, sym.size, freq.ctypes.data,
+                                   freq.shape[0], out.ctypes.data, cap)
+    if n < 0:
+        raise LicError(n, "lic_rans_ileave_encode")
+    return out[:n].tobytes()
+
+
+def rans_ileave_decode(data: bytes, tab, freq, n: int, lanes: int = 8) -> np.ndarray:
+    tab = np.ascontiguousarray(tab, np.uint8).ravel()
+    freq = np.ascontiguousarray(freq, np.uint32)
+    buf = np.frombuffer(data, np.uint8).copy() if data else np.zeros(1, np.uint8)
+    sym = np.empty(max(n, 1), np.uint8)
+    rc = lib.lic_rans_ileave_decode(lanes, buf.ctypes.data, len(data), tab.ctypes.data, n, freq.ctypes.data,
+                                    freq.shape[0], sym.ctypes.data)
+    if rc != 0:
+        raise LicError(rc, "lic_rans_ileave_decode")
+    return sym[:n]
 
 
 def fnv1a(data: bytes) -> int:

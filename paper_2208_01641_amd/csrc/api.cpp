@@ -76,6 +76,8 @@ void codec_default_config(codec_config* cfg)
     cfg->hbm_budget_bytes = 0;
     cfg->hip_device = 0;
     cfg->use_graphs = 1;
+    cfg->norm = LIC_NORM_GDN;
+    cfg->rans_lanes = 0;
 }
 
 int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, codec_t** out)
@@ -90,6 +92,11 @@ int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, cod
     }
     if (cfg->hs_out != LIC_HS_EXP && cfg->hs_out != LIC_HS_RELU) { g_create_error = "bad hs_out"; return LIC_E_ARG; }
     if (cfg->gs_mode < 0 || cfg->gs_mode > 2) { g_create_error = "gs_mode must be 0, 1 or 2"; return LIC_E_ARG; }
+    if (cfg->norm != LIC_NORM_GDN && cfg->norm != LIC_NORM_1DN) { g_create_error = "bad norm"; return LIC_E_ARG; }
+    if (cfg->rans_lanes != 0 && !lic::rans_lanes_valid(cfg->rans_lanes)) {
+        g_create_error = "rans_lanes must be 0, 2, 4, 8, 16 or 32";
+        return LIC_E_ARG;
+    }
     if (cfg->y_slices < 1 || cfg->y_slices > lic::kMaxSlices) { g_create_error = "y_slices must be 1..64"; return LIC_E_ARG; }
     if (cfg->entropy_threads < 1 || cfg->entropy_threads > 256) { g_create_error = "bad entropy_threads"; return LIC_E_ARG; }
     if (cfg->max_in_flight < 1 || cfg->max_in_flight > 64) { g_create_error = "max_in_flight must be 1..64"; return LIC_E_ARG; }
@@ -153,7 +160,8 @@ int parse_all(Codec* c, const uint8_t* bits, const size_t* lens, int n, lic::Cal
         std::string e;
         if (!lic::parse_stream(bits + off, lens[i], &h, &(*zp)[i], &(*zl)[i], &(*yp)[i], &(*yl)[i], &e))
             return fail(c, LIC_E_CORRUPT, e);
-        if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id)
+        if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id ||
+            h.norm != c->norm || h.lanes != c->lanes)
             return fail(c, LIC_E_MODEL, "bitstream was produced by another model");
         if (h.S > lic::kMaxSlices) return fail(c, LIC_E_CORRUPT, "too many slices");
         if (h.H != (*hdrs)[0].H || h.W != (*hdrs)[0].W || h.S != (*hdrs)[0].S)
@@ -379,6 +387,41 @@ int lic_rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n, c
     return LIC_OK;
 }
 
+long lic_rans_ileave_encode(int lanes, const uint8_t* sym, const uint8_t* tab, long n, const uint32_t* freq, int ntab,
+                            uint8_t* out, size_t cap)
+{
+    if (!lic::rans_lanes_valid(lanes) || n < 0 || ntab < 1 || ntab > 256 || (n > 0 && (!sym || !tab)) || !freq ||
+        !out)
+        return LIC_E_ARG;
+    for (long i = 0; i < n; ++i)
+        if (sym[i] >= lic::kNumSym || tab[i] >= ntab) return LIC_E_ARG;
+    lic::TableSet T;
+    T.init(ntab, freq, false);
+    for (int t = 0; t < ntab; ++t)
+        if (T.start[(size_t)t * (lic::kNumSym + 1) + lic::kNumSym] != (1u << lic::kPrecBits)) return LIC_E_ARG;
+    std::vector<int8_t> v(n);
+    for (long i = 0; i < n; ++i) v[i] = (int8_t)((int)sym[i] + lic::kSymMin);
+    long len = lic::rans_ileave_encode(lanes, v.data(), tab, n, T, out, cap);
+    return len < 0 ? LIC_E_SMALLBUF : len;
+}
+
+int lic_rans_ileave_decode(int lanes, const uint8_t* in, size_t len, const uint8_t* tab, long n, const uint32_t* freq,
+                           int ntab, uint8_t* sym)
+{
+    if (!lic::rans_lanes_valid(lanes) || n < 0 || ntab < 1 || ntab > 256 || !in || !freq || (n > 0 && (!tab || !sym)))
+        return LIC_E_ARG;
+    for (long i = 0; i < n; ++i)
+        if (tab[i] >= ntab) return LIC_E_ARG;
+    lic::TableSet T;
+    T.init(ntab, freq, true);
+    for (int t = 0; t < ntab; ++t)
+        if (T.start[(size_t)t * (lic::kNumSym + 1) + lic::kNumSym] != (1u << lic::kPrecBits)) return LIC_E_ARG;
+    std::vector<int8_t> v(n);
+    if (lic::rans_ileave_decode(lanes, in, len, tab, n, T, v.data()) != 0) return LIC_E_CORRUPT;
+    for (long i = 0; i < n; ++i) sym[i] = (uint8_t)((int)v[i] - lic::kSymMin);
+    return LIC_OK;
+}
+
 uint32_t lic_fnv1a(const void* data, size_t len) { return lic::fnv1a(data, len); }
 
 int codec_open_stream(codec_t* c, int H, int W, int* stream_id)
@@ -422,7 +465,8 @@ int codec_submit_decode(codec_t* c, int stream_id, const uint8_t* bits, size_t l
         return fail(c, LIC_E_CORRUPT, e);
     }
     const lic::StreamHeader& h = r->hdr;
-    if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id) {
+    if (h.kind != c->kind || h.N != c->N || h.M != c->M || h.hs_exp != c->hs_exp || h.model_id != c->model_id ||
+            h.norm != c->norm || h.lanes != c->lanes) {
         delete r;
         return fail(c, LIC_E_MODEL, "bitstream was produced by another model");
     }

@@ -266,6 +266,8 @@ struct Codec {
     codec_config cfg{};
     std::string err;
     int kind = 1, N = 128, M = 192, hs_exp = 1, S = 8;
+    int norm = 0;                      // 0 GDN / IGDN, 1 1DN (container flag bit 1)
+    int lanes = 0;                     // rANS: 0 byte-wise one state, K interleaved states
     uint32_t model_id = 0;
     std::vector<float> medians;        // channel offsets of the factorized tables
     TableSet fact;                     // [C] factorized tables

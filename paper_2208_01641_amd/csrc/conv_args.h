@@ -74,6 +74,8 @@ struct ConvArgs {
     int Co;                  // real output channels
     int nphase, ncog;        // phases, output-channel groups
     int hs_exp;              // EP_INDEX: 1 = thresholds are ln(t_k), else t_k with ReLU
+    int norm1;               // EP_GDN / EP_IGDN: 1 = 1DN, n = beta + gamma |x|, y = x / n
+                             // (inverse y = x n); 0 = GDN, n = beta + gamma (x*x), y = x / sqrt(n)
     int Hc, Wc;              // EP_RGB crop size
     int kk, pad;             // LD_RGB kernel size and padding
     const float* rscale;     // DT_FP8: per packed row, weight scale x input scale

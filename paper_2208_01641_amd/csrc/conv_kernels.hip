@@ -11,8 +11,9 @@
 //   loaders  : float NHWC, |float| NHWC (h_a input), int8 symbols + per-channel
 //              offset (dequantisation of y_hat / z_hat), and the 3-channel NCHW
 //              image with the 64-multiple zero padding done by bounds checks.
-//   epilogues: bias, ReLU, GDN / IGDN (channel-mixing sum as a second MFMA
-//              contraction on the registers of the first), quantisation to
+//   epilogues: bias, ReLU, GDN / IGDN or 1DN (channel-mixing sum of x^2, or
+//              of |x| for 1DN, as a second MFMA contraction on the registers
+//              of the first), quantisation to
 //              int8 symbols, scale-table index, and the final clamp + crop.
 //
 // GEMM view: rows = output channels (MFMA A operand, packed weights), columns
@@ -1048,8 +1049,9 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     };
 
     if constexpr (EP == EP_GDN || EP == EP_IGDN) {
-        // n = beta + gamma (x*x): [Co x Co] x [Co x pixels] on the bf16 matrix
-        // cores with FP32 accumulation.  x*x and gamma are each split into
+        // n = beta + gamma (x*x) (1DN: beta + gamma |x|): [Co x Co] x [Co x
+        // pixels] on the bf16 matrix cores with FP32 accumulation.  x*x (|x|)
+        // and gamma are each split into
         // bf16 parts rounded to nearest (v = v0 + v1 + v2 + e, |e| <= 2^-27 |v|;
         // gamma's parts are precomputed); the products of parts whose orders
         // sum to at most GP - 1 are kept: six for the FP32 form (relative error
@@ -1116,7 +1118,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const float x = acc[2 * p + i / 4][nt][i % 4];
-                    float r = x * x;
+                    float r = a.norm1 ? fabsf(x) : x * x;
 #pragma unroll
                     for (int g = 0; g < GP; ++g) {
                         uint32_t u = __float_as_uint(r);
@@ -1171,9 +1173,13 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     // GDN: x times the hardware reciprocal square root (within
-                    // about one ulp; n >= beta > 0), IGDN: x sqrt(n)
-                    y[i] = (EP == EP_GDN) ? acc[mt][nt][i] * __builtin_amdgcn_rsqf(nacc[mt][nt][i])
-                                          : acc[mt][nt][i] * sqrtf(nacc[mt][nt][i]);
+                    // about one ulp; n >= beta > 0), IGDN: x sqrt(n); 1DN: x
+                    // times the hardware reciprocal (about one ulp), inverse x n
+                    const float nv = nacc[mt][nt][i];
+                    if (EP == EP_GDN)
+                        y[i] = acc[mt][nt][i] * (a.norm1 ? __builtin_amdgcn_rcpf(nv) : __builtin_amdgcn_rsqf(nv));
+                    else
+                        y[i] = acc[mt][nt][i] * (a.norm1 ? nv : sqrtf(nv));
                 }
                 if (pv[nt]) store_act(obase[nt] + mt * 16 + kg * 4, y);
             }

@@ -228,7 +228,175 @@ int decode_impl(const uint8_t* in, size_t len, long n, const TableSet& T, int8_t
     return (x == kRansLow && pos == len) ? 0 : -1;
 }
 
+// ------------------------------------------------- interleaved rANS
+// K states share one stream of 16-bit words (state range [2^16, 2^32)):
+// symbol i is coded by state i mod K, so K independent dependency chains run
+// side by side in one thread.  The encoder walks the symbols backwards and
+// writes words at decreasing addresses, which leaves them in the reverse of
+// the order it pushed them; the decoder, walking forwards, reads each state's
+// words in the reverse of that state's pushes from the one shared stream.
+// Stream: the K final states (u32 LE, state 0 first), then the words (u16 LE).
+// Each state pushes at most one word per symbol (x < 2^32 <= f 2^32 / f), so
+// a whole group of K symbols never needs more than 2K bytes: the loops check
+// the room once per group and run branch-free inside it.
+constexpr uint32_t kWordLow = 1u << 16;
+
+template <int K, class TabOf>
+long encode_ileave(const int8_t* sym, long n, const TableSet& T, uint8_t* out, size_t cap, TabOf tab_of)
+{
+    uint32_t x[K];
+    for (int j = 0; j < K; ++j) x[j] = kWordLow;
+    long pos = (long)cap;
+    const uint32_t* __restrict__ freq = T.freq.data();
+    const uint32_t* __restrict__ start = T.start.data();
+    const uint64_t* __restrict__ rcp = T.rcp.data();
+    // codes symbol i with state xj; with `room` the word is stored unchecked
+    auto put = [&](uint32_t& xj, long i, bool room) __attribute__((always_inline)) -> bool {
+        const int t = tab_of(i);
+        const int a = (int)sym[i] - kSymMin;
+        const size_t k = (size_t)t * kNumSym + a;
+        const uint32_t f = freq[k];
+        const uint32_t push = xj >= (f << kPrecBits) ? 1u : 0u;
+        if (!room) {
+            if (push) {
+                if (pos < 2) return false;
+                out[pos - 2] = (uint8_t)xj;
+                out[pos - 1] = (uint8_t)(xj >> 8);
+            }
+        } else {
+            out[pos - 2] = (uint8_t)xj;
+            out[pos - 1] = (uint8_t)(xj >> 8);
+        }
+        pos -= 2 * (long)push;
+        xj = push ? xj >> 16 : xj;
+        const uint32_t q = f == 1 ? xj : (uint32_t)(((unsigned __int128)xj * rcp[k]) >> 64);
+        xj = xj + start[(size_t)t * (kNumSym + 1) + a] + q * ((1u << kPrecBits) - f);
+        return true;
+    };
+    const long groups = n / K;
+    for (long i = n - 1; i >= groups * K; --i)
+        if (!put(x[i % K], i, false)) return -1;
+    for (long g = groups - 1; g >= 0; --g) {
+        const long i0 = g * K;
+        if (pos >= 2L * K) {
+#pragma GCC unroll 32
+            for (int j = K - 1; j >= 0; --j) put(x[j], i0 + j, true);
+        } else {
+            for (int j = K - 1; j >= 0; --j)
+                if (!put(x[j], i0 + j, false)) return -1;
+        }
+    }
+    if (pos < 4L * K) return -1;
+    pos -= 4L * K;
+    for (int j = 0; j < K; ++j) {
+        out[pos + 4 * j + 0] = (uint8_t)x[j];
+        out[pos + 4 * j + 1] = (uint8_t)(x[j] >> 8);
+        out[pos + 4 * j + 2] = (uint8_t)(x[j] >> 16);
+        out[pos + 4 * j + 3] = (uint8_t)(x[j] >> 24);
+    }
+    const long len = (long)cap - pos;
+    memmove(out, out + pos, (size_t)len);
+    return len;
+}
+
+template <int K, class TabOf>
+int decode_ileave(const uint8_t* in, size_t len, long n, const TableSet& T, int8_t* sym, TabOf tab_of)
+{
+    if (len < 4u * K) return -1;
+    uint32_t x[K];
+    for (int j = 0; j < K; ++j)
+        x[j] = (uint32_t)in[4 * j] | ((uint32_t)in[4 * j + 1] << 8) | ((uint32_t)in[4 * j + 2] << 16) |
+               ((uint32_t)in[4 * j + 3] << 24);
+    size_t pos = 4u * K;
+    const uint32_t mask = (1u << kPrecBits) - 1;
+    const uint32_t* __restrict__ freq = T.freq.data();
+    const uint32_t* __restrict__ start = T.start.data();
+    // decodes symbol i from state xj; with `room` the word is read unchecked
+    auto get = [&](uint32_t& xj, long i, bool room) __attribute__((always_inline)) -> bool {
+        const int t = tab_of(i);
+        const uint32_t slot = xj & mask;
+        const int a = find_symbol(T, t, slot);
+        sym[i] = (int8_t)(a + kSymMin);
+        xj = freq[(size_t)t * kNumSym + a] * (xj >> kPrecBits) + slot - start[(size_t)t * (kNumSym + 1) + a];
+        const bool refill = xj < kWordLow;
+        if (!room) {
+            if (!refill) return true;
+            if (pos + 2 > len) return false;
+        }
+        const uint32_t w = (uint32_t)in[pos] | ((uint32_t)in[pos + 1] << 8);
+        xj = refill ? (xj << 16) | w : xj;
+        pos += refill ? 2 : 0;
+        return true;
+    };
+    const long groups = n / K;
+    for (long g = 0; g < groups; ++g) {
+        const long i0 = g * K;
+        if (pos + 2u * K <= len) {
+#pragma GCC unroll 32
+            for (int j = 0; j < K; ++j) get(x[j], i0 + j, true);
+        } else {
+            for (int j = 0; j < K; ++j)
+                if (!get(x[j], i0 + j, false)) return -1;
+        }
+    }
+    for (long i = groups * K; i < n; ++i)
+        if (!get(x[i % K], i, false)) return -1;
+    for (int j = 0; j < K; ++j)
+        if (x[j] != kWordLow) return -1;
+    return pos == len ? 0 : -1;
+}
+
+template <class TabOf>
+long encode_ileave_k(int K, const int8_t* sym, long n, const TableSet& T, uint8_t* out, size_t cap, TabOf tab_of)
+{
+    switch (K) {
+    case 2: return encode_ileave<2>(sym, n, T, out, cap, tab_of);
+    case 4: return encode_ileave<4>(sym, n, T, out, cap, tab_of);
+    case 8: return encode_ileave<8>(sym, n, T, out, cap, tab_of);
+    case 16: return encode_ileave<16>(sym, n, T, out, cap, tab_of);
+    case 32: return encode_ileave<32>(sym, n, T, out, cap, tab_of);
+    }
+    return -2;
+}
+
+template <class TabOf>
+int decode_ileave_k(int K, const uint8_t* in, size_t len, long n, const TableSet& T, int8_t* sym, TabOf tab_of)
+{
+    switch (K) {
+    case 2: return decode_ileave<2>(in, len, n, T, sym, tab_of);
+    case 4: return decode_ileave<4>(in, len, n, T, sym, tab_of);
+    case 8: return decode_ileave<8>(in, len, n, T, sym, tab_of);
+    case 16: return decode_ileave<16>(in, len, n, T, sym, tab_of);
+    case 32: return decode_ileave<32>(in, len, n, T, sym, tab_of);
+    }
+    return -2;
+}
+
 }  // namespace
+
+bool rans_lanes_valid(int K) { return K == 2 || K == 4 || K == 8 || K == 16 || K == 32; }
+
+long rans_ileave_encode(int K, const int8_t* sym, const uint8_t* tab, long n, const TableSet& T, uint8_t* out,
+                        size_t cap)
+{
+    return encode_ileave_k(K, sym, n, T, out, cap, [tab](long i) { return (int)tab[i]; });
+}
+
+long rans_ileave_encode_channel(int K, const int8_t* sym, long n, int C, const TableSet& T, uint8_t* out, size_t cap)
+{
+    return encode_ileave_k(K, sym, n, T, out, cap, [C](long i) { return (int)(i % C); });
+}
+
+int rans_ileave_decode(int K, const uint8_t* in, size_t len, const uint8_t* tab, long n, const TableSet& T,
+                       int8_t* sym)
+{
+    return decode_ileave_k(K, in, len, n, T, sym, [tab](long i) { return (int)tab[i]; });
+}
+
+int rans_ileave_decode_channel(int K, const uint8_t* in, size_t len, long n, int C, const TableSet& T, int8_t* sym)
+{
+    return decode_ileave_k(K, in, len, n, T, sym, [C](long i) { return (int)(i % C); });
+}
 
 long rans_encode(const int8_t* sym, const uint8_t* tab, long n, const TableSet& T, uint8_t* out, size_t cap)
 {
@@ -278,7 +446,9 @@ void write_header(uint8_t* out, const StreamHeader& h, uint32_t len_z, const uin
     memcpy(out, "LICS", 4);
     out[4] = 1;
     out[5] = (uint8_t)h.kind;
-    out[6] = (uint8_t)(h.hs_exp & 1);
+    int lg = 0;
+    while (h.lanes > 1 && (1 << lg) < h.lanes) ++lg;
+    out[6] = (uint8_t)((h.hs_exp & 1) | ((h.norm & 1) << 1) | ((lg & 7) << 2));
     out[7] = (uint8_t)h.S;
     put16(out + 8, h.H);
     put16(out + 10, h.W);
@@ -297,6 +467,9 @@ bool parse_stream(const uint8_t* bits, size_t len, StreamHeader* h, const uint8_
     if (bits[4] != 1) { *err = "unsupported bitstream version"; return false; }
     h->kind = bits[5];
     h->hs_exp = bits[6] & 1;
+    h->norm = (bits[6] >> 1) & 1;
+    h->lanes = (bits[6] >> 2) & 7 ? 1 << ((bits[6] >> 2) & 7) : 0;
+    if ((bits[6] & 0xe0) != 0 || (h->lanes && !rans_lanes_valid(h->lanes))) { *err = "unknown bitstream flags"; return false; }
     h->S = bits[7];
     h->H = (int)get16(bits + 8);
     h->W = (int)get16(bits + 10);

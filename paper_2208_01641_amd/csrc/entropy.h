@@ -60,14 +60,32 @@ int rans_decode(const uint8_t* in, size_t len, const uint8_t* tab, long n, const
 int rans_decode_channel(const uint8_t* in, size_t len, long n, int C, const TableSet& T,
                         int8_t* sym);
 
+// Interleaved word-wise rANS with K states (K = 2, 4, 8, 16 or 32; symbol i
+// on state i mod K, 32-bit states in [2^16, 2^32), 16-bit words, one shared
+// stream: the K final states, then the words).  Same return values as above;
+// a stream of n symbols takes at most 2 n + 4 K bytes.
+bool rans_lanes_valid(int K);
+long rans_ileave_encode(int K, const int8_t* sym, const uint8_t* tab, long n, const TableSet& T, uint8_t* out,
+                        size_t cap);
+long rans_ileave_encode_channel(int K, const int8_t* sym, long n, int C, const TableSet& T, uint8_t* out, size_t cap);
+int rans_ileave_decode(int K, const uint8_t* in, size_t len, const uint8_t* tab, long n, const TableSet& T,
+                       int8_t* sym);
+int rans_ileave_decode_channel(int K, const uint8_t* in, size_t len, long n, int C, const TableSet& T, int8_t* sym);
+
 uint32_t fnv1a(const void* data, size_t len);
 
 // ---------------------------------------------------------------- container
+// flags: bit 0 exp output of h_s, bit 1 1DN instead of GDN, bits 2..4 log2 of
+// the interleaved rANS states (0: byte-wise single-state rANS), bits 5..7 zero
 struct StreamHeader {
     int kind = 1, hs_exp = 1, S = 1, H = 0, W = 0, N = 0, M = 0;
+    int norm = 0, lanes = 0;
     uint32_t model_id = 0;
 };
 constexpr size_t kHeaderBytes = 20;
+// room beyond 2 bytes per symbol that one rANS stream may need (the final
+// states: 4 bytes byte-wise, 4 K interleaved)
+constexpr size_t kStreamSlack = 160;
 inline size_t header_size(int kind, int S) { return kHeaderBytes + 4u * (S + (kind == 1 ? 1 : 0)); }
 void write_header(uint8_t* out, const StreamHeader& h, uint32_t len_z, const uint32_t* len_y);
 // Validates and returns the payload spans; false on any inconsistency.

@@ -204,6 +204,8 @@ int Codec::load(const void* blob, size_t len)
     N = cfg.N;
     M = cfg.M;
     hs_exp = cfg.hs_out == LIC_HS_EXP ? 1 : 0;
+    norm = cfg.norm;
+    lanes = cfg.rans_lanes;
     S = cfg.y_slices;
     model_id = fnv1a(blob, len);
 
@@ -485,6 +487,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.Co = L.co;
     a.nphase = L.nphase;
     a.hs_exp = hs_exp;
+    a.norm1 = norm;
     a.Hc = d.H;
     a.Wc = d.W;
     a.kk = L.k;

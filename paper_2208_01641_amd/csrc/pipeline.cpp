@@ -67,7 +67,7 @@ static int stage_gpu_index(StageKind k)
 
 // worst case rANS output: 2 bytes per symbol (f = 1) + 4 state bytes per
 // stream; regions of the per-frame scratch: z first, then each y slice
-static size_t scratch_bytes(size_t ny, size_t nz) { return 2 * (ny + nz) + 16 * (kMaxSlices + 1); }
+static size_t scratch_bytes(size_t ny, size_t nz) { return 2 * (ny + nz) + kStreamSlack * (kMaxSlices + 1); }
 
 // ----------------------------------------------------------------- start
 int Codec::start()
@@ -544,6 +544,14 @@ static inline void slice_rows(int Hy, int S, int s, int* r0, int* r1)
     *r1 = (int)((long)(s + 1) * Hy / S);
 }
 
+// Offset of y slice si (latent rows from r0) in a frame's rANS scratch: the
+// z stream's region comes first, then one region per slice, each 2 bytes per
+// symbol plus kStreamSlack.
+static inline size_t y_region(int kind, size_t nz, size_t row, int r0, int si)
+{
+    return (kind == 1 ? 2 * nz + kStreamSlack : 0) + 2 * (size_t)r0 * row + kStreamSlack * (size_t)si;
+}
+
 int Codec::cpu_job(Task* t, int b, int part)
 {
     const FrameDims& d = t->route->dims;
@@ -558,7 +566,8 @@ int Codec::cpu_job(Task* t, int b, int part)
     uint8_t* scratch = s.h_scratch + (size_t)b * s.scratch_per_frame;
     if (k == ST_CPU_ENC) {
         if (kind == 1 && part == 0) {
-            long len = rans_encode_channel(sym_z, (long)nz, N, fact, scratch, 2 * nz + 16);
+            long len = lanes ? rans_ileave_encode_channel(lanes, sym_z, (long)nz, N, fact, scratch, 2 * nz + kStreamSlack)
+                             : rans_encode_channel(sym_z, (long)nz, N, fact, scratch, 2 * nz + kStreamSlack);
             if (len < 0) { t->fail(LIC_E_STATE, "rANS z overflow"); return LIC_E_STATE; }
             t->part_len[b][0] = (size_t)len;
             return LIC_OK;
@@ -566,17 +575,24 @@ int Codec::cpu_job(Task* t, int b, int part)
         const int si = part - (kind == 1 ? 1 : 0);
         int r0, r1;
         slice_rows(d.Hy, S, si, &r0, &r1);
-        uint8_t* region = scratch + (kind == 1 ? 2 * nz + 16 : 0) + 2 * (size_t)r0 * row + 16 * (size_t)si;
-        const size_t cap = 2 * (size_t)(r1 - r0) * row + 16;
+        uint8_t* region = scratch + y_region(kind, nz, row, r0, si);
+        const size_t cap = 2 * (size_t)(r1 - r0) * row + kStreamSlack;
         const size_t off = (size_t)r0 * row, cnt = (size_t)(r1 - r0) * row;
-        long len = kind == 1 ? rans_encode(sym_y + off, idx + off, (long)cnt, gauss, region, cap)
-                             : rans_encode_channel(sym_y + off, (long)cnt, M, fact, region, cap);
+        long len;
+        if (lanes)
+            len = kind == 1 ? rans_ileave_encode(lanes, sym_y + off, idx + off, (long)cnt, gauss, region, cap)
+                            : rans_ileave_encode_channel(lanes, sym_y + off, (long)cnt, M, fact, region, cap);
+        else
+            len = kind == 1 ? rans_encode(sym_y + off, idx + off, (long)cnt, gauss, region, cap)
+                            : rans_encode_channel(sym_y + off, (long)cnt, M, fact, region, cap);
         if (len < 0) { t->fail(LIC_E_STATE, "rANS y overflow"); return LIC_E_STATE; }
         t->part_len[b][part] = (size_t)len;
         return LIC_OK;
     }
     if (k == ST_CPU_DEC_Z) {
-        if (rans_decode_channel(t->zp[b], t->zlen[b], (long)nz, N, fact, sym_z) != 0) {
+        const int rc = lanes ? rans_ileave_decode_channel(lanes, t->zp[b], t->zlen[b], (long)nz, N, fact, sym_z)
+                             : rans_decode_channel(t->zp[b], t->zlen[b], (long)nz, N, fact, sym_z);
+        if (rc != 0) {
             t->fail(LIC_E_CORRUPT, "corrupt z stream");
             return LIC_E_CORRUPT;
         }
@@ -586,7 +602,14 @@ int Codec::cpu_job(Task* t, int b, int part)
         int r0, r1;
         slice_rows(d.Hy, S, part, &r0, &r1);
         const size_t off = (size_t)r0 * row, cnt = (size_t)(r1 - r0) * row;
-        int rc = kind == 1 ? rans_decode(t->yp[b][part], t->ylen[b][part], idx + off, (long)cnt, gauss, sym_y + off)
+        int rc;
+        if (lanes)
+            rc = kind == 1 ? rans_ileave_decode(lanes, t->yp[b][part], t->ylen[b][part], idx + off, (long)cnt, gauss,
+                                                sym_y + off)
+                           : rans_ileave_decode_channel(lanes, t->yp[b][part], t->ylen[b][part], (long)cnt, M, fact,
+                                                        sym_y + off);
+        else
+            rc = kind == 1 ? rans_decode(t->yp[b][part], t->ylen[b][part], idx + off, (long)cnt, gauss, sym_y + off)
                            : rans_decode_channel(t->yp[b][part], t->ylen[b][part], (long)cnt, M, fact, sym_y + off);
         if (rc != 0) {
             t->fail(LIC_E_CORRUPT, "corrupt y stream");
@@ -610,6 +633,8 @@ int Codec::cpu_finalize(Task* t, StageKind k)
     StreamHeader h;
     h.kind = kind;
     h.hs_exp = hs_exp;
+    h.norm = norm;
+    h.lanes = lanes;
     h.S = S;
     h.H = d.H;
     h.W = d.W;
@@ -641,7 +666,7 @@ int Codec::cpu_finalize(Task* t, StageKind k)
         for (int i = 0; i < S; ++i) {
             int r0, r1;
             slice_rows(d.Hy, S, i, &r0, &r1);
-            const uint8_t* region = scratch + (kind == 1 ? 2 * nz + 16 : 0) + 2 * (size_t)r0 * row + 16 * (size_t)i;
+            const uint8_t* region = scratch + y_region(kind, nz, row, r0, i);
             memcpy(p, region, ylen[i]);
             t->yp[b][i] = p;
             t->ylen[b][i] = ylen[i];

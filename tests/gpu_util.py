@@ -50,7 +50,7 @@ def make_codec(kind=1, N=128, M=192, gamma="diag", hs_out=1, seed=synth.WEIGHT_S
     P = synth.model_params(kind, N, M, seed=seed, gamma=gamma)
     blob = synth.weight_blob(P, kind, N, M)
     c = Codec(blob, kind=kind, N=N, M=M, hs_out=hs_out, **kw)
-    m = oracle.Model(P, kind, N, M, blob, hs_out=hs_out)
+    m = oracle.Model(P, kind, N, M, blob, hs_out=hs_out, norm=kw.get("norm", 0), lanes=kw.get("rans_lanes", 0))
     return c, m
 
 

@@ -95,3 +95,49 @@ def test_library_rans_hand_example_and_errors(L):
     bad[0] = 2                     # does not sum to 2^16
     with pytest.raises(LicError):
         rans_encode(np.zeros(3, np.uint8), np.zeros(3, np.uint8), bad[None])
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(0, 2 ** 31), st.integers(0, 3000), st.integers(1, 64), st.sampled_from([2, 4, 8, 16, 32]))
+def test_library_interleaved_rans_bytes_equal_oracle(seed, n, ntab, lanes):
+    from paper_2208_01641_amd import rans_ileave_decode, rans_ileave_encode
+    freq = _tables(seed, ntab)
+    rng = np.random.default_rng(seed + 2)
+    tab = rng.integers(0, ntab, n).astype(np.uint8)
+    sym = np.array([rng.choice(129, p=freq[t] / 65536.0) for t in tab], np.uint8)
+    lib_bytes = rans_ileave_encode(sym, tab, freq, lanes)
+    assert lib_bytes == oracle.rans_ileave_encode(sym.astype(np.int32), tab.astype(np.int32), freq, K=lanes)
+    assert len(lib_bytes) <= 2 * n + 4 * lanes
+    assert np.array_equal(rans_ileave_decode(lib_bytes, tab, freq, n, lanes), sym)
+
+
+def test_library_interleaved_rans_golden_and_errors(L):
+    """The hand-worked streams of the interleaved coder, the unchecked (room
+    for a whole group) and checked paths on long and short streams, and
+    rejection of truncated, extended and mis-laned streams."""
+    import json
+    from paper_2208_01641_amd import LicError, rans_ileave_decode, rans_ileave_encode
+    with open(os.path.join(ROOT, "tests", "golden", "rans_ileave_hand.json")) as fh:
+        cases = json.load(fh)["cases"]
+    for c in cases:
+        f = np.zeros(129, np.uint32)
+        f[:len(c["freq_head"])] = c["freq_head"]
+        sym = np.array(c["sym"], np.uint8)
+        got = rans_ileave_encode(sym, np.zeros_like(sym), f[None], c["K"])
+        assert got == bytes.fromhex(c["bytes_hex"].replace(" ", "")), c["name"]
+    f = np.ones(129, np.uint32)
+    f[64] = 65536 - 128
+    rng = np.random.default_rng(3)
+    sym = rng.integers(0, 129, 1001).astype(np.uint8)      # mostly f = 1: a word per symbol
+    tab = np.zeros_like(sym)
+    data = rans_ileave_encode(sym, tab, f[None], 8)
+    assert np.array_equal(rans_ileave_decode(data, tab, f[None], sym.size, 8), sym)
+    for bad in (data[:-2], data + b"\x00\x00", data[:-1]):
+        with pytest.raises(LicError):
+            rans_ileave_decode(bad, tab, f[None], sym.size, 8)
+    with pytest.raises(LicError):
+        rans_ileave_decode(data, tab, f[None], sym.size, 4)
+    with pytest.raises(LicError):
+        rans_ileave_encode(sym, tab, f[None], 3)
+    # empty input: the K initial states alone
+    assert rans_ileave_encode(np.zeros(0, np.uint8), np.zeros(0, np.uint8), f[None], 4) == bytes.fromhex("00000100" * 4)

@@ -74,3 +74,34 @@ def test_decode_rejects_other_model(hyper_model):
     other = oracle.Model(P, 1, 128, 192, synth.weight_blob(P, 1, 128, 192))
     with pytest.raises(ValueError):
         other.decode(bits)
+
+
+@pytest.mark.parametrize("kind,lanes", [(1, 8), (0, 4)])
+def test_interleaved_coder_round_trip_and_flag(kind, lanes):
+    """With the interleaved coder the codec round trip is unchanged: the same
+    symbols, the same rate up to the coders' per-stream overhead, and the
+    coder recorded in flag bits 2..4 of the container."""
+    P = synth.model_params(kind, 128, 192)
+    blob = synth.weight_blob(P, kind, 128, 192)
+    byte = oracle.Model(P, kind, 128, 192, blob)
+    il = oracle.Model(P, kind, 128, 192, blob, lanes=lanes)
+    x = synth.frame_sinusoid(96, 160)
+    b0, e0 = byte.encode(x, S=2)
+    b1, e1 = il.encode(x, S=2)
+    assert np.array_equal(e0["sym_y"], e1["sym_y"])
+    hdr = oracle.parse_container(b1)
+    assert hdr["lanes"] == lanes and oracle.parse_container(b0)["lanes"] == 0
+    assert b1[6] >> 2 == lanes.bit_length() - 1
+    xr, dec = il.decode(b1)
+    assert np.array_equal(dec["yhat"], e0["yhat"])
+    # each stream pays at most 4 lanes + 1 bytes of states beyond the byte-wise coder's
+    nstreams = 2 + (1 if kind == 1 else 0)
+    assert abs(len(b1) - len(b0)) <= nstreams * (4 * lanes + 8) + len(b0) // 50
+    with pytest.raises(ValueError):
+        byte.decode(b1)
+    with pytest.raises(ValueError):
+        il.decode(b0)
+    bad = bytearray(b1)
+    bad[6] |= 0x80            # an undefined flag bit
+    with pytest.raises(ValueError):
+        oracle.parse_container(bytes(bad))
