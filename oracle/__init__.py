@@ -107,8 +107,15 @@ def lib():
         L.or_rans_ileave_encode.argtypes = [P, P, l, i, P, P, l]
         L.or_rans_ileave_decode.restype = i
         L.or_rans_ileave_decode.argtypes = [P, l, P, l, i, P, P]
+        L.or_set_threads.restype = i
+        L.or_set_threads.argtypes = [i]
         _lib = L
     return _lib
+
+
+def set_threads(n: int = 0) -> int:
+    """Sets the OpenMP threads of the oracle's loops (0: leave); returns the count."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def _p(a: np.ndarray):

@@ -29,9 +29,18 @@
  * force, closed forms, identities, round trips); see the test files.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+
+/* OpenMP threads of the parallel loops below (timing runs on a chosen core
+ * count); returns the count in effect. */
+int or_set_threads(int n)
+{
+    if (n > 0) omp_set_num_threads(n);
+    return omp_get_max_threads();
+}
 
 /* ------------------------------------------------------------------------ */
 /* Convolution (NCHW, zero outside the input)                                */
