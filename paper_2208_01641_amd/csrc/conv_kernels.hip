@@ -120,25 +120,34 @@ template <> struct Prec<DT_FP8> {
     static constexpr int KCH = 128, KE = 32, WMUL = 1;
 };
 
-// eight FP32 values as three bf16 parts (rounded to nearest, remainders exact)
-__device__ __forceinline__ Split3 split3(const float (&v)[8])
+// eight FP32 values as G bf16 parts, each rounded to nearest (v_cvt_pk_bf16_f32,
+// two values per instruction) from what the previous parts leave, which is
+// exact in FP32: v = v0 + ... + v_{G-1} up to the rounding of the last part
+template <int G>
+__device__ __forceinline__ void split_parts(const float (&v)[8], bf16x8 (&out)[G])
 {
     typedef float f2 __attribute__((ext_vector_type(2)));
     typedef __bf16 b2 __attribute__((ext_vector_type(2)));
-    u32x4 w[3];
+    u32x4 w[G];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
         f2 r = {v[2 * j], v[2 * j + 1]};
 #pragma unroll
-        for (int g = 0; g < 3; ++g) {
+        for (int g = 0; g < G; ++g) {
             const b2 h = __builtin_convertvector(r, b2);
             w[g][j] = __builtin_bit_cast(uint32_t, h);
-            if (g < 2) r -= __builtin_convertvector(h, f2);
+            if (g + 1 < G) r -= __builtin_convertvector(h, f2);
         }
     }
-    Split3 s;
 #pragma unroll
-    for (int g = 0; g < 3; ++g) s.p[g] = __builtin_bit_cast(bf16x8, w[g]);
+    for (int g = 0; g < G; ++g) out[g] = __builtin_bit_cast(bf16x8, w[g]);
+}
+
+// eight FP32 values as three bf16 parts (v = v0 + v1 + v2 up to 2^-27 |v|)
+__device__ __forceinline__ Split3 split3(const float (&v)[8])
+{
+    Split3 s;
+    split_parts<3>(v, s.p);
     return s;
 }
 
@@ -452,6 +461,23 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         }
     };
 
+    // Addresses of the gathered loaders: each pixel's window origin (tap
+    // offset 0) is computed once; a tap adds (dy Win + dx) CIN elements and
+    // the bounds test compares the origin row / column with the image, so
+    // the K loop has no 64-bit multiplies per tap.
+    constexpr long InE = LD == LD_I8 ? 1 : (long)sizeof(Elem);      // bytes per input element
+    int oy0[NT], ox0[NT];
+    const uint8_t* pbase[NT];
+    if constexpr (LD != LD_RGB && LD != LD_TILE) {
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            oy0[nt] = gy[nt] * a.s_in;
+            ox0[nt] = gx[nt] * a.s_in;
+            pbase[nt] = static_cast<const uint8_t*>(a.in) +
+                        ((((long)img[nt] * a.Hin + oy0[nt]) * a.Win + ox0[nt]) * CIN + (DT == DT_FP8 ? 0 : kg * KE)) * InE;
+        }
+    }
+
     // DT_FP8: chunk kc of the flattened (tap, channel) axis; this lane group
     // takes channels c .. c + 31 of tap t (t >= ntaps: past the end, zeros)
     auto loadA8 = [&](int kc, Frag (&A)[MT]) __attribute__((always_inline)) {
@@ -506,13 +532,14 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             } else {
                 const int tv = __builtin_amdgcn_ds_bpermute(4 * (t < ntaps ? t : 0), tapv);
                 const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
-                const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
-                const bool ok = t < ntaps && pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-                const long off = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + c;
+                const bool ok = t < ntaps && pv[nt] && (unsigned)(oy0[nt] + dy) < (unsigned)a.Hin &&
+                                (unsigned)(ox0[nt] + dx) < (unsigned)a.Win;
+                const int off = (dy * a.Win + dx) * CIN + c;              // from the window origin
                 {
                     if constexpr (LD == LD_I8) {
                         // y_hat = symbol + offset, rounded to e4m3 (exact for |y_hat| <= 16)
-                        const int8_t* src = ok ? static_cast<const int8_t*>(a.in) + off : static_cast<const int8_t*>(a.zero);
+                        const int8_t* src = ok ? reinterpret_cast<const int8_t*>(pbase[nt]) + off
+                                               : static_cast<const int8_t*>(a.zero);
                         const float* mu = ok ? a.mu_in + c : static_cast<const float*>(a.zero);
                         const uint4 u0 = *reinterpret_cast<const uint4*>(src);
                         const uint4 u1 = *reinterpret_cast<const uint4*>(src + 16);
@@ -523,7 +550,8 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
                                          (float)(int8_t)(w[q] >> 16) + mu[4 * q + 2],
                                          (float)(int8_t)(w[q] >> 24) + mu[4 * q + 3]);
                     } else {
-                        const Elem* src = ok ? static_cast<const Elem*>(a.in) + off : static_cast<const Elem*>(a.zero);
+                        const Elem* src = ok ? reinterpret_cast<const Elem*>(pbase[nt]) + off
+                                             : static_cast<const Elem*>(a.zero);
                         v = *reinterpret_cast<const Frag*>(src);
                     }
                 }
@@ -572,17 +600,17 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // come in exactly the cursor's order.
     constexpr bool kCursor = DT != DT_FP8 && LD != LD_RGB;
     int cur_t = kslot % ntaps, cur_kc = kslot / ntaps;
-    long pixoff[NT];
+    // (the tap offset is the same for every lane: dy, dx come from readlane,
+    // so it stays on the scalar unit)
+    long toff = 0;                                                   // tap offset in elements
     bool pok[NT];
     auto set_tap = [&](int t) __attribute__((always_inline)) {
         const int tv = __builtin_amdgcn_readlane(tapv, t < ntaps ? t : 0);
         const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
+        toff = ((long)dy * a.Win + dx) * CIN;
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const int iy = gy[nt] * a.s_in + dy, ix = gx[nt] * a.s_in + dx;
-            pok[nt] = pv[nt] && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-            pixoff[nt] = (((long)img[nt] * a.Hin + iy) * a.Win + ix) * CIN + kg * KE;
-        }
+        for (int nt = 0; nt < NT; ++nt)
+            pok[nt] = pv[nt] && (unsigned)(oy0[nt] + dy) < (unsigned)a.Hin && (unsigned)(ox0[nt] + dx) < (unsigned)a.Win;
     };
     if constexpr (kCursor) set_tap(cur_t);
     auto cursor_loadB = [&](BRaw (&B)[NT]) __attribute__((always_inline)) {
@@ -590,7 +618,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
             if constexpr (LD == LD_I8) {
-                const int8_t* src = pok[nt] ? static_cast<const int8_t*>(a.in) + pixoff[nt] + cur_kc * KCH
+                const int8_t* src = pok[nt] ? reinterpret_cast<const int8_t*>(pbase[nt] + toff + cur_kc * KCH)
                                             : static_cast<const int8_t*>(a.zero);
                 const float* mu = pok[nt] ? a.mu_in + cur_kc * KCH + kg * KE : static_cast<const float*>(a.zero);
                 I8Raw r;
@@ -605,7 +633,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
                 for (int e = 0; e < KE; e += 4) *reinterpret_cast<f4*>(&r.mu[e]) = *reinterpret_cast<const f4*>(mu + e);
                 B[nt] = r;
             } else {
-                const Elem* src = pok[nt] ? static_cast<const Elem*>(a.in) + pixoff[nt] + cur_kc * KCH
+                const Elem* src = pok[nt] ? reinterpret_cast<const Elem*>(pbase[nt] + (toff + cur_kc * KCH) * InE)
                                           : static_cast<const Elem*>(a.zero);
                 B[nt] = *reinterpret_cast<const BIn*>(src);
             }
@@ -1114,26 +1142,16 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             bf16x8 S[GP][NT];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
-                uint32_t sb[GP][8];
+                float r[8];
 #pragma unroll
                 for (int i = 0; i < 8; ++i) {
                     const float x = acc[2 * p + i / 4][nt][i % 4];
-                    float r = a.norm1 ? fabsf(x) : x * x;
-#pragma unroll
-                    for (int g = 0; g < GP; ++g) {
-                        uint32_t u = __float_as_uint(r);
-                        u = (u + 0x7fffu + ((u >> 16) & 1u)) & 0xffff0000u;
-                        sb[g][i] = u;
-                        r -= __uint_as_float(u);        // exact: u is r to 8 bits
-                    }
+                    r[i] = a.norm1 ? fabsf(x) : x * x;
                 }
+                bf16x8 parts[GP];
+                split_parts<GP>(r, parts);
 #pragma unroll
-                for (int g = 0; g < GP; ++g) {
-                    u32x4 w;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j) w[j] = (sb[g][2 * j] >> 16) | sb[g][2 * j + 1];
-                    S[g][nt] = __builtin_bit_cast(bf16x8, w);
-                }
+                for (int g = 0; g < GP; ++g) S[g][nt] = parts[g];
             }
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt) {
