@@ -190,7 +190,9 @@ int codec_poll(codec_t* c, lic_result* done, int max, int timeout_us);
 /* hyper-latents Hp/64 x Wp/64).  All tensors are NHWC except images.        */
 /*                                                                          */
 /*  In the BF16 form the NHWC activations in and out of GA0..GA2 and       */
-/*  GS0..GS2 (and into GA3 / GS3) are bf16; y, z, v and images stay f32.    */
+/*  GS0..GS2 (and into GA3 / GS3) are bf16; in the FP8 form they are e4m3   */
+/*  bytes (8 x value) except GS2's output (into GS3), bf16; y, z, v and     */
+/*  images stay f32.  codec_layer_bytes gives every buffer's size.          */
 /*  layer          in                         out                aux         */
 /*  LIC_GA0..GA2   ga0: image NCHW f32         NHWC f32           -           */
 /*  LIC_GA3        NHWC f32                    y NHWC f32         sym_y int8  */
@@ -225,6 +227,14 @@ int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float
 
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
                     const void* in, void* out, void* aux);
+/* Bytes codec_run_layer reads from in and writes to out / aux for n frames
+ * of H x W in this codec's form (0: the layer takes no such buffer; aux is
+ * optional where the table above says so).  Element sizes: images, y, z,
+ * v and the hyper activations float32, symbols int8, indices uint8, the
+ * GDN layers' activations float32 (FP32 form), bf16 (BF16 form), or e4m3
+ * (FP8 form; GS2 stores bf16 there, read by GS3 on bf16 operands). */
+int codec_layer_bytes(codec_t* c, int layer, int n, int H, int W, size_t* in_bytes,
+                      size_t* out_bytes, size_t* aux_bytes);
 
 /* Kernel timing inside the pipeline: every launch of a layer whose bit is
  * set in mask (bit i = layer i) is bracketed with HIP events on the stream

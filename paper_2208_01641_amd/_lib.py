@@ -90,6 +90,7 @@ SIGNATURES = {
     "codec_tables": (c_long, [P, c_int, P, c_size_t]),
     "codec_time_layers": (c_int, [P, c_uint32]),
     "codec_layer_kernel": (c_int, [P, c_int, c_int, c_int, P, P]),
+    "codec_layer_bytes": (c_int, [P, c_int, c_int, c_int, c_int, P, P, P]),
     "codec_layer_time": (c_int, [P, c_int, P, P]),
     "codec_medians": (c_long, [P, P, c_size_t]),
     "lic_rans_encode": (c_long, [P, P, c_long, P, c_int, P, c_size_t]),

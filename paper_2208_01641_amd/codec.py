@@ -134,8 +134,24 @@ class Codec:
         v = np.ascontiguousarray(params, np.float32)
         self._check(lib.codec_load_distilled(self._h, v.ctypes.data, v.size, judge_psnr_db, judge_every))
 
+    def layer_bytes(self, layer, n: int, H: int, W: int):
+        """(in, out, aux) bytes of codec_run_layer's buffers for this layer."""
+        lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
+        b = (ctypes.c_size_t * 3)()
+        self._check(lib.codec_layer_bytes(self._h, lid, n, H, W, ctypes.byref(b, 0), ctypes.byref(b, 8),
+                                          ctypes.byref(b, 16)))
+        return tuple(int(v) for v in b)
+
     def run_layer(self, layer, n: int, H: int, W: int, inp, out, aux=None):
         lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
+        # refuse buffers smaller than what the layer reads or writes
+        need = self.layer_bytes(lid, n, H, W)
+        for name, t, nb in (("input", inp, need[0]), ("output", out, need[1]), ("aux", aux, need[2])):
+            if t is None or nb == 0:
+                continue
+            have = t.numel() * t.element_size() if hasattr(t, "element_size") else t.nbytes
+            if have < nb:
+                raise LicError(_lib.LIC_E_SMALLBUF, f"{_lib.LAYERS[lid]} {name} buffer holds {have} bytes, needs {nb}")
         _sync(inp, out, aux)
         self._check(lib.codec_run_layer(self._h, lid, n, H, W, _ptr(inp), 0 if out is None else _ptr(out),
                                         0 if aux is None else _ptr(aux)))

@@ -300,6 +300,16 @@ int codec_run_layer(codec_t* c, int layer, int n, int H, int W, const void* in, 
     return LIC_OK;
 }
 
+int codec_layer_bytes(codec_t* c, int layer, int n, int H, int W, size_t* in_bytes, size_t* out_bytes,
+                      size_t* aux_bytes)
+{
+    if (!c || !in_bytes || !out_bytes || !aux_bytes) return LIC_E_ARG;
+    if (layer < 0 || layer >= LIC_NUM_LAYERS || !c->layers[layer].present) return fail(c, LIC_E_ARG, "no such layer");
+    if (n < 1 || H < 1 || W < 1 || H > 65535 || W > 65535) return fail(c, LIC_E_ARG, "bad size");
+    c->layer_bytes(layer, n, lic::FrameDims(H, W), in_bytes, out_bytes, aux_bytes);
+    return LIC_OK;
+}
+
 int codec_layer_kernel(codec_t* c, int layer, int H, int W, int* form, int* ksplit)
 {
     if (!c || !form || !ksplit) return LIC_E_ARG;

@@ -33,6 +33,7 @@ struct LayerGPU {
     int nphase = 1;
     bool halo1 = false;                // every tap within one pixel of a stride-1 grid
     bool out_e4m3 = false;             // bf16 GEMM storing e4m3 activations (e4m3 form, image layer)
+    bool out_bf16 = false;             // e4m3 GEMM storing bf16 activations (e4m3 form, GS2)
     std::vector<PhaseDesc> host_ph;
     PhaseDesc* d_ph = nullptr;
     uint8_t* d_w = nullptr;            // packed weights (float, bf16 or e4m3)
@@ -331,6 +332,9 @@ struct Codec {
     int load(const void* blob, size_t len);
     int build_layers(const std::map<std::string, std::pair<std::vector<int>, std::vector<double>>>& P);
     Geo geo(int layer, const FrameDims& d) const;
+    // Bytes of a layer's input, output and aux tensors for n frames of d
+    // (codec_run_layer's buffers; 0 where the layer takes none).
+    void layer_bytes(int layer, int n, const FrameDims& d, size_t* in, size_t* out, size_t* aux) const;
     int launch_layer(int layer, int n, const FrameDims& d, const void* in, void* out, void* aux,
                      hipStream_t s, std::string* errp, KernelKey* chosen = nullptr);
     // pools and threads

@@ -565,11 +565,11 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     auto store_act = [&](long idx, const f4& y) __attribute__((always_inline)) {
         if constexpr (DT == DT_F32 || DT == DT_F32X) {
             *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
-        } else if constexpr (DT == DT_FP8) {
+        } else if (DT == DT_FP8 && !a.out_bf16) {
             const float q = a.out_q;
             *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
                 e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
-        } else if (a.out_e4m3) {
+        } else if (DT == DT_BF16 && a.out_e4m3) {
             const float q = a.out_q;
             *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
                 e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
@@ -1418,7 +1418,6 @@ static const KernelEntry kEntries[] = {
     LIC_KGF(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KGF(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
     LIC_KGF(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGF(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
-    LIC_KF(LIC_GS3, 128, 1, 4, 4, LD_F32, EP_RGB), LIC_KF(LIC_GS3, 192, 1, 4, 4, LD_F32, EP_RGB),
     // distilled synthesis network (64 hidden channels): forward in FP32 or
     // bf16 operands, input gradients (ReLU-masked) in FP32
     LIC_K2(TAG_DT1, 192, LD_I8, EP_RELU), LIC_K2(TAG_DT1, 320, LD_I8, EP_RELU),

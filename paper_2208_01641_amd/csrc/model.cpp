@@ -313,6 +313,11 @@ int Codec::build_layers(const ParamMap& P)
         // chunk; pixel values keep 8 bits), e4m3 activations out
         L.out_e4m3 = L.dt == DT_FP8 && sp.ld == LD_RGB;
         if (L.out_e4m3) L.dt = DT_BF16;
+        // and its output layer too (bf16 halo tiles: the 3 output channels
+        // make a K chunk of 128 (tap, channel) pairs a poor fit), fed by a
+        // last GDN layer that stores bf16
+        if (L.dt == DT_FP8 && sp.id == LIC_GS3) L.dt = DT_BF16;
+        L.out_bf16 = L.dt == DT_FP8 && sp.id == LIC_GS2;
         // 75 (tap, channel) pairs in whole K chunks
         const int krgb = L.dt == DT_FP8 ? 128 : 96;
         L.cin = sp.ld == LD_RGB ? krgb : ci;
@@ -455,6 +460,48 @@ Geo Codec::geo(int id, const FrameDims& d) const
     return {0, 0, 0, 0, 0, 0, 0, 0};
 }
 
+// Element size of the activations a layer stores (the GDN layers' forms).
+static size_t act_bytes(const LayerGPU& L)
+{
+    if (L.dt == DT_F32 || L.dt == DT_F32X) return 4;
+    if (L.dt == DT_BF16) return L.out_e4m3 ? 1 : 2;
+    return L.out_bf16 ? 2 : 1;
+}
+
+void Codec::layer_bytes(int id, int n, const FrameDims& d, size_t* in, size_t* out, size_t* aux) const
+{
+    const Geo g = geo(id, d);
+    const size_t nn = (size_t)n;
+    const size_t img = nn * 3 * d.H * d.W;
+    const size_t px_in = nn * g.Hin * g.Win, px_out = nn * g.Hout * g.Wout;
+    *aux = 0;
+    // input: the image, int8 symbols, y / z / hyper activations (FP32), or
+    // the previous layer's stored activations
+    if (id == LIC_GA0) *in = img * 4;
+    else if (id == LIC_HS0 || id == LIC_GS0) *in = px_in * layers[id].cin;
+    else if (id >= LIC_HA0 && id <= LIC_HS2) *in = px_in * layers[id].cin * 4;
+    else *in = px_in * layers[id].cin * act_bytes(layers[id - 1]);
+    switch (id) {
+    case LIC_GA3: case LIC_HA2:                       // float values, int8 symbols
+        *out = px_out * layers[id].co * 4;
+        *aux = px_out * layers[id].co;
+        break;
+    case LIC_HS2:                                     // uint8 indices, float values
+        *out = px_out * layers[id].co;
+        *aux = px_out * layers[id].co * 4;
+        break;
+    case LIC_GS3:                                     // cropped image, padded pre-clamp image
+        *out = img * 4;
+        *aux = nn * 3 * d.Hp * d.Wp * 4;
+        break;
+    case LIC_HA0: case LIC_HA1: case LIC_HS0: case LIC_HS1:
+        *out = px_out * layers[id].co * 4;
+        break;
+    default:                                          // GDN layers
+        *out = px_out * layers[id].co * act_bytes(layers[id]);
+    }
+}
+
 int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void* out, void* aux, hipStream_t s,
                         std::string* errp, KernelKey* chosen)
 {
@@ -495,6 +542,7 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.rscale = L.d_rscale;
     a.out_q = kActQ;
     a.out_e4m3 = L.out_e4m3 ? 1 : 0;
+    a.out_bf16 = L.out_bf16 ? 1 : 0;
 
     const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase, L.halo1 && g.s_in == 1 ? 1 : 0};
     return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp, chosen);
@@ -538,12 +586,15 @@ int launch_conv_policy(const ConvShape& L, ConvArgs& a, long policy_pixels, hipS
     } else {
         // 64-channel x 32-pixel wave tiles; when the grid of one image gives
         // fewer than 2 waves per SIMD, split K over 4 or 8 waves of a block;
-        // only the tiniest layers fall back to 16 x 16 tiles (split 8).  The
+        // grids of fewer than 128 such tiles (the 24 x 40 and 12 x 20 hyper
+        // layers of a 720p frame) take 16 x 16 tiles (split 8) instead, for
+        // 8 times the blocks (measured: h_a's second layer 44 -> 30 us, h_s's
+        // first 22 -> 16 us; the 48 x 80 layers are slower that way).  The
         // choice depends on the per-image size only, so a frame gives the
         // same bits alone or in a batch (split-K changes the summation order).
         const long tiles_big = ((policy_pixels + 31) / 32) * L.nphase * (L.cop / 64);
         key.mt = 4; key.nt = 2;
-        if (L.cop % 64 != 0 || tiles_big < 32) {
+        if (L.cop % 64 != 0 || tiles_big < 128) {
             key.mt = 1; key.nt = 1; key.waves = 8; key.ksplit = 8;
         } else if (tiles_big >= 2048) {
             key.waves = 4; key.ksplit = 1;

@@ -31,21 +31,20 @@ def _chain(prec, H, W, t=7):
     f = Form(prec)
     c, m = make_codec(1, N, M, gamma="dense", precision=prec, max_h=H, max_w=W, max_in_flight=1, norm=1)
     x = synth.frame_sinusoid(H, W, t=t)
-    dt = f.dtype(torch)
     shp = lambda L: (1,) + layer_out_shape(L, H, W, N, M)
     o = {"x": x}
-    o["GA0"] = torch.empty(shp("GA0"), device="cuda", dtype=dt)
+    o["GA0"] = torch.empty(shp("GA0"), device="cuda", dtype=f.dtype(torch, "GA0"))
     c.run_layer("GA0", 1, H, W, torch.from_numpy(x)[None].cuda(), o["GA0"])
     for L, src in (("GA1", "GA0"), ("GA2", "GA1")):
-        o[L] = torch.empty(shp(L), device="cuda", dtype=dt)
+        o[L] = torch.empty(shp(L), device="cuda", dtype=f.dtype(torch, L))
         c.run_layer(L, 1, H, W, o[src], o[L])
     o["GA3"] = torch.empty(shp("GA3"), device="cuda")
     o["sym"] = torch.empty(shp("GA3"), device="cuda", dtype=torch.int8)
     c.run_layer("GA3", 1, H, W, o["GA2"], o["GA3"], o["sym"])
-    o["GS0"] = torch.empty(shp("GS0"), device="cuda", dtype=dt)
+    o["GS0"] = torch.empty(shp("GS0"), device="cuda", dtype=f.dtype(torch, "GS0"))
     c.run_layer("GS0", 1, H, W, o["sym"], o["GS0"])
     for L, src in (("GS1", "GS0"), ("GS2", "GS1")):
-        o[L] = torch.empty(shp(L), device="cuda", dtype=dt)
+        o[L] = torch.empty(shp(L), device="cuda", dtype=f.dtype(torch, L))
         c.run_layer(L, 1, H, W, o[src], o[L])
     torch.cuda.synchronize()
     c.close()
@@ -94,11 +93,11 @@ def test_reduced_forms_1dn_sampled_720p(prec):
         w = f.w_first(P["ga0.w"]) if i == 0 else f.w(P[f"ga{i}.w"], "conv")
         ref = oracle.conv2d_points(src, w, P[f"ga{i}.b"], 2, 2, pts)
         ref = oracle.gdn1(ref.T, P[f"ga{i}.beta"], P[f"ga{i}.gamma"]).T
-        if prec == 2:
+        if prec == 2 and L != "GS2":
             assert 8 * np.max(np.abs(ref)) < 448, "e4m3 activations would saturate"
         err = _rel(_sampled(out, pts), ref)
         print(f"{L}: max error / max |ref| = {err:.2e}")
-        assert err < f.tol, L
+        assert err < f.tolerance(L), L
         src = out
     src = f.yhat(np.transpose(o["sym"][0].cpu().numpy(), (2, 0, 1)).astype(np.float64))
     for i, L in enumerate(("GS0", "GS1", "GS2")):
@@ -106,11 +105,11 @@ def test_reduced_forms_1dn_sampled_720p(prec):
         pts = _points(out.shape[1], out.shape[2], np.random.default_rng(41 + i))
         ref = oracle.deconv2d_points(src, f.w(P[f"gs{i}.w"], "deconv"), P[f"gs{i}.b"], 2, 2, pts)
         ref = oracle.gdn1(ref.T, P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True).T
-        if prec == 2:
+        if prec == 2 and L != "GS2":
             assert 8 * np.max(np.abs(ref)) < 448, "e4m3 activations would saturate"
         err = _rel(_sampled(out, pts), ref)
         print(f"{L}: max error / max |ref| = {err:.2e}")
-        assert err < f.tol, L
+        assert err < f.tolerance(L), L
         src = out
 
 

@@ -27,7 +27,7 @@ CHAIN = [("GA0", "x", "act", None), ("GA1", "GA0", "act", None), ("GA2", "GA1", 
          ("GA3", "GA2", "f32", "i8"), ("HA0", "GA3", "f32", None), ("HA1", "HA0", "f32", None),
          ("HA2", "HA1", "f32", "i8"), ("HS0", "HA2:aux", "f32", None), ("HS1", "HS0", "f32", None),
          ("HS2", "HS1", "u8", "f32"), ("GS0", "GA3:aux", "act", None), ("GS1", "GS0", "act", None),
-         ("GS2", "GS1", "act", None), ("GS3", "GS2", "img", "pre")]
+         ("GS2", "GS1", "act_gs2", None), ("GS3", "GS2", "img", "pre")]
 
 
 @pytest.mark.parametrize("prec,N,M,H,W,n", CASES, ids=lambda v: str(v))
@@ -36,7 +36,9 @@ def test_layers_batched_equal_single(prec, N, M, H, W, n):
     assert torch.cuda.is_available()
     c, _ = make_codec(1, N, M, gamma="dense", precision=prec, max_h=H, max_w=W, max_in_flight=1, max_batch=n)
     act = {0: torch.float32, 1: torch.bfloat16, 2: torch.uint8}[prec]
-    dt = {"act": act, "f32": torch.float32, "u8": torch.uint8, "i8": torch.int8}
+    # (the e4m3 form's GS2 stores bf16 for its output layer's bf16 operands)
+    dt = {"act": act, "act_gs2": torch.bfloat16 if prec == 2 else act, "f32": torch.float32, "u8": torch.uint8,
+          "i8": torch.int8}
     Hp, Wp = 64 * -(-H // 64), 64 * -(-W // 64)
 
     def alloc(L, key, k):

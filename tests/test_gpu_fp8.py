@@ -3,7 +3,8 @@
 The GEMM operands are e4m3: weights w8 = e4m3(w / s_row) with one FP32 scale
 per output row (s_row = max |w| of the row / 448), activations between layers
 stored as e4m3(8 x value), y_hat converted in the loader; the image layer
-runs on bf16 operands and stores e4m3 activations.
+runs on bf16 operands and stores e4m3 activations, and so does the output
+layer, whose input the last GDN layer of g_s (GS2) stores in bf16.
 Products of e4m3 values are exact in FP32, so the oracle runs in FP64 on the
 same dequantised operands: what remains is FP32 accumulation (float outputs
 within 1e-4) and, for layers that store e4m3 activations, one e4m3 rounding
@@ -18,7 +19,7 @@ import oracle
 import synth
 from gpu_util import chw, layer_out_shape, make_codec, rel_err
 from test_gpu_codec import _expected_stream
-from test_gpu_precision import bf16
+from test_gpu_precision import BF16_OUT_TOL, bf16, chw_any
 
 pytestmark = pytest.mark.gpu
 
@@ -128,18 +129,24 @@ def test_fp8_synthesis_layers(torch_dev, N, M, H, W):
     prev = torch.from_numpy(np.ascontiguousarray(np.transpose(sym, (1, 2, 0)))[None]).cuda()
     src = e4m3(sym.astype(np.float64))
     for i, L in ((0, "GS0"), (1, "GS1"), (2, "GS2")):
-        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda", dtype=torch.uint8)
+        # GS2 stores bf16 (the output layer's operands), the others e4m3
+        o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda",
+                        dtype=torch.bfloat16 if L == "GS2" else torch.uint8)
         c.run_layer(L, 1, H, W, prev, o)
         ref = oracle.gdn(oracle.deconv2d(src, w_fp8(P[f"gs{i}.w"], "deconv"), P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
-        assert np.max(np.abs(ref)) * Q < 448, L
-        assert rel_err(act(o), ref) < FP8_OUT_TOL, L
+        if L == "GS2":
+            assert rel_err(chw_any(o), ref) < BF16_OUT_TOL, L
+            src = chw_any(o)
+        else:
+            assert np.max(np.abs(ref)) * Q < 448, L
+            assert rel_err(act(o), ref) < FP8_OUT_TOL, L
+            src = act(o)
         prev = o
-        src = act(o)
     img = torch.empty((1, 3, H, W), device="cuda")
     pre = torch.empty((1, 3, 64 * -(-H // 64), 64 * -(-W // 64)), device="cuda")
     c.run_layer("GS3", 1, H, W, prev, img, pre)
-    ref = oracle.deconv2d(src, w_fp8(P["gs3.w"], "rows"), P["gs3.b"], 2, 2, 1)
+    ref = oracle.deconv2d(src, bf16(P["gs3.w"]), P["gs3.b"], 2, 2, 1)
     assert rel_err(pre[0].cpu().numpy(), ref) < 1e-4
     assert np.max(np.abs(img[0].cpu().numpy() - np.clip(ref, 0, 1)[:, :H, :W])) <= 1e-3
     c.close()
@@ -191,4 +198,6 @@ def test_fp8_codec_rate_distortion_vs_fp64(torch_dev):
           f"dbpp {d_bpp:+.5f}")
     assert abs(d_psnr) <= 0.1
     assert abs(d_bpp) <= 0.05 * oracle.bpp(len(bits64), H, W)
+    # fidelity to the FP64 codec's own reconstruction: ~24 dB measured at 720p
+    assert oracle.psnr(x64, xf) >= 20.0
     c.close()

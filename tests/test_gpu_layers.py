@@ -203,3 +203,14 @@ def test_layer_kernel_forms(torch_dev):
     assert c.layer_kernel("GA1", 720, 1280) == ("bf16", 1)
     assert c.layer_kernel("HA1", 720, 1280)[0] == "f32"       # the hyper path stays FP32
     c.close()
+    c, _ = make_codec(1, 128, 192, precision=2, max_h=720, max_w=1280, max_in_flight=1)
+    assert c.layer_kernel("GA1", 720, 1280) == ("fp8", 1)
+    assert c.layer_kernel("GS2", 720, 1280) == ("fp8", 1)
+    assert c.layer_kernel("GA0", 720, 1280) == ("bf16", 1)    # image layer: bf16 operands
+    assert c.layer_kernel("GS3", 720, 1280) == ("bf16", 1)    # output layer: bf16 halo tiles
+    # GS2 stores bf16 for it; the other GDN layers e4m3 bytes
+    n_px = 384 * 640 * 128
+    assert c.layer_bytes("GS2", 1, 720, 1280)[1] == 2 * n_px
+    assert c.layer_bytes("GS3", 1, 720, 1280)[0] == 2 * n_px
+    assert c.layer_bytes("GA0", 1, 720, 1280)[1] == n_px
+    c.close()

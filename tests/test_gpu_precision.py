@@ -145,4 +145,8 @@ def test_bf16_codec_rate_distortion_vs_fp64(torch_dev):
           f"dbpp {d_bpp:+.5f}")
     assert abs(d_psnr) <= 0.1
     assert abs(d_bpp) <= 0.01 * oracle.bpp(len(bits64), H, W)
+    # fidelity to the FP64 codec's own reconstruction (the random-weight
+    # codec is ~7 dB from the source, so the gap above barely moves): ~36 dB
+    # measured at 720p
+    assert oracle.psnr(x64, xb) >= 30.0
     c.close()
