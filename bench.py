@@ -205,6 +205,8 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
                   max_batch=batch, norm=norm, rans_lanes=rans_lanes)
     frames = synth.frames_sinusoid_torch(H, W, range(steps + warmup), device="cuda")
     out = torch.empty_like(frames)
+    if precision == 2:                    # e4m3 activation scales from a calibration frame of the stream
+        codec.calibrate(synth.frames_sinusoid_torch(H, W, [10_000], device="cuda"))
     if kind == 0 and (H, W) == (128, 128):   # the factorized-prior case: 1/f-spectrum noise images
         frames = torch.from_numpy(np.stack([synth.image_1f(H, W, seed=1641 + i)
                                             for i in range(steps + warmup)])).cuda()

@@ -225,6 +225,22 @@ enum {
 int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float judge_psnr_db,
                          int judge_every);
 
+/* FP8 form: sets the activation scale of every layer that stores e4m3
+ * activations from calibration frames x (n x 3 x H x W float32 in [0, 1],
+ * host or device): the layer's activations are stored as e4m3(q * value)
+ * with q = 448 / (2 amax), amax the largest |value| the layer produces on
+ * these frames (layers calibrated in order, each with its predecessors'
+ * scales in place); the reading layer undoes q in its epilogue.  Until the
+ * first call every q is 8.  Other forms: no effect.  Encoders and decoders
+ * must use the same scales for identical reconstructions (the bitstream does
+ * not carry them).  Call while no work is in flight; captured serving graphs
+ * are dropped. */
+int codec_calibrate(codec_t* c, const float* x, int n, int H, int W, int is_device);
+/* FP8 form: q of each layer (LIC_NUM_LAYERS entries; 0 for layers that do
+ * not store e4m3) and, if saturated != NULL, the number of values the e4m3
+ * stores have clamped to +-448 since create.  Returns LIC_NUM_LAYERS. */
+int codec_fp8_scales(const codec_t* c, float* q, int max, unsigned long long* saturated);
+
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
                     const void* in, void* out, void* aux);
 /* Bytes codec_run_layer reads from in and writes to out / aux for n frames

@@ -105,6 +105,8 @@ SIGNATURES = {
     "codec_submit_decode": (c_int, [P, c_int, P, c_size_t, P, c_size_t, c_int, P]),
     "codec_poll": (c_int, [P, P, c_int, c_int]),
     "codec_load_distilled": (c_int, [P, P, c_size_t, ctypes.c_float, c_int]),
+    "codec_calibrate": (c_int, [P, P, c_int, c_int, c_int, c_int]),
+    "codec_fp8_scales": (c_int, [P, P, c_int, P]),
     "lic_distill_default_config": (None, [P]),
     "lic_distill_param_count": (c_size_t, [c_int, c_int]),
     "lic_distill_create": (c_int, [P, P, c_size_t, P]),

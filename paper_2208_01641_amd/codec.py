@@ -134,6 +134,20 @@ class Codec:
         v = np.ascontiguousarray(params, np.float32)
         self._check(lib.codec_load_distilled(self._h, v.ctypes.data, v.size, judge_psnr_db, judge_every))
 
+    def calibrate(self, x):
+        """FP8 form: per-layer e4m3 activation scales from frames x [n, 3, H, W]."""
+        n, _, H, W = x.shape
+        _sync(x)
+        self._check(lib.codec_calibrate(self._h, _ptr(x), n, H, W, _is_device(x)))
+
+    def fp8_scales(self):
+        """(q per layer, as a list of LIC_NUM_LAYERS floats (0: no e4m3 output),
+        values clamped to +-448 by e4m3 stores since create)."""
+        q = np.zeros(len(_lib.LAYERS), np.float32)
+        sat = ctypes.c_ulonglong()
+        self._check(lib.codec_fp8_scales(self._h, q.ctypes.data, q.size, ctypes.byref(sat)))
+        return q.tolist(), int(sat.value)
+
     def layer_bytes(self, layer, n: int, H: int, W: int):
         """(in, out, aux) bytes of codec_run_layer's buffers for this layer."""
         lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)

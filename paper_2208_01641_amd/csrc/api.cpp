@@ -274,6 +274,47 @@ int codec_get_stats(const codec_t* c, char* buf, size_t cap)
     return n;
 }
 
+int codec_calibrate(codec_t* c, const float* x, int n, int H, int W, int is_device)
+{
+    if (!c || !x) return LIC_E_ARG;
+    int rc;
+    if (!check_frame(c, n, H, W, &rc)) return rc;
+    if (n < 1) return fail(c, LIC_E_ARG, "no calibration frames");
+    if (hipSetDevice(c->cfg.hip_device) != hipSuccess) return fail(c, LIC_E_HIP, "hipSetDevice");
+    const float* xd = x;
+    void* tmp = nullptr;
+    const size_t bytes = (size_t)n * 3 * H * W * sizeof(float);
+    if (!is_device) {
+        if (hipMalloc(&tmp, bytes) != hipSuccess) return fail(c, LIC_E_NOMEM, "calibration input");
+        if (hipMemcpy(tmp, x, bytes, hipMemcpyHostToDevice) != hipSuccess) {
+            (void)hipFree(tmp);
+            return fail(c, LIC_E_HIP, "calibration input copy");
+        }
+        xd = static_cast<const float*>(tmp);
+    }
+    rc = c->calibrate_fp8(xd, n, H, W);
+    if (tmp) (void)hipFree(tmp);
+    if (rc != LIC_OK) return fail(c, rc, c->err);
+    return LIC_OK;
+}
+
+int codec_fp8_scales(const codec_t* c, float* q, int max, unsigned long long* saturated)
+{
+    if (!c || (!q && max > 0)) return LIC_E_ARG;
+    for (int i = 0; i < std::min(max, (int)LIC_NUM_LAYERS); ++i) {
+        const lic::LayerGPU& L = c->layers[i];
+        const bool e8 = L.present && (L.dt == lic::DT_FP8 ? !L.out_bf16 : L.out_e4m3);
+        q[i] = e8 ? L.out_q : 0.0f;
+    }
+    if (saturated) {
+        *saturated = 0;
+        if (c->d_sat && (hipSetDevice(c->cfg.hip_device) != hipSuccess ||
+                         hipMemcpy(saturated, c->d_sat, sizeof(*saturated), hipMemcpyDeviceToHost) != hipSuccess))
+            return LIC_E_HIP;
+    }
+    return LIC_NUM_LAYERS;
+}
+
 int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float judge_psnr_db, int judge_every)
 {
     if (!c || !params) return LIC_E_ARG;

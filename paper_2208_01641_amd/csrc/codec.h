@@ -34,6 +34,9 @@ struct LayerGPU {
     bool halo1 = false;                // every tap within one pixel of a stride-1 grid
     bool out_e4m3 = false;             // bf16 GEMM storing e4m3 activations (e4m3 form, image layer)
     bool out_bf16 = false;             // e4m3 GEMM storing bf16 activations (e4m3 form, GS2)
+    float out_q = 8.0f;                // e4m3 activations out hold out_q x the value
+    float in_scale = 1.0f;             // e4m3 form: 1 / out_q of the layer whose e4m3 output this reads
+    std::vector<float> wsc;            // e4m3 form: per packed row, the weight scale
     std::vector<PhaseDesc> host_ph;
     PhaseDesc* d_ph = nullptr;
     uint8_t* d_w = nullptr;            // packed weights (float, bf16 or e4m3)
@@ -46,7 +49,8 @@ struct LayerGPU {
     const float* d_mu_in = nullptr;    // LD_I8 offsets
 };
 
-// e4m3 activations between layers hold kActQ x the value (|value| <= 56 fits)
+// e4m3 activations between layers hold q x the value: kActQ (|value| <= 56
+// fits) until codec_calibrate sets each layer's q from calibration frames
 constexpr float kActQ = 8.0f;
 uint8_t e4m3_rne(float f);
 std::vector<uint16_t> gdn_gamma_split(const std::vector<double>& gamma, int co);
@@ -337,6 +341,11 @@ struct Codec {
     void layer_bytes(int layer, int n, const FrameDims& d, size_t* in, size_t* out, size_t* aux) const;
     int launch_layer(int layer, int n, const FrameDims& d, const void* in, void* out, void* aux,
                      hipStream_t s, std::string* errp, KernelKey* chosen = nullptr);
+    // e4m3 form: per-row scales of a layer's epilogue (weight scale x input scale)
+    int upload_rscale(LayerGPU& L);
+    // e4m3 form: activation scales from calibration frames (device, n x 3 x H x W)
+    int calibrate_fp8(const float* x, int n, int H, int W);
+    unsigned long long* d_sat = nullptr;     // e4m3 stores clamped at +-448 (counter)
     // pools and threads
     int start();
     void stop();

@@ -82,6 +82,7 @@ struct ConvArgs {
     float out_q;             // DT_FP8: activations are stored as e4m3(out_q * value)
     int out_e4m3;            // DT_BF16 kernels: store e4m3(out_q * value) instead of bf16
                              // (the e4m3 form's image layer runs on bf16 operands)
+    unsigned long long* sat; // e4m3 stores: count of values clamped to +-448 (null: not counted)
     int out_bf16;            // DT_FP8 kernels: store bf16 instead of e4m3 (the e4m3 form's
                              // last GDN layer feeds an output layer on bf16 operands)
 };

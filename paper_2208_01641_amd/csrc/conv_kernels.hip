@@ -561,18 +561,23 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
       }
     };
 
+    // values an e4m3 store clamps to +-448, counted once per wave (rare: the
+    // activation scales are calibrated so that it does not happen)
+    auto count_sat = [&](const f4& v) __attribute__((always_inline)) {
+        if (!a.sat) return;
+        const bool s = fabsf(v[0]) > 448.0f || fabsf(v[1]) > 448.0f || fabsf(v[2]) > 448.0f || fabsf(v[3]) > 448.0f;
+        const unsigned long long m = __ballot(s);
+        if (m && lane == __ffsll((long long)m) - 1) atomicAdd(a.sat, (unsigned long long)__popcll(m));
+    };
     // stores 4 consecutive channels of one pixel in the activation storage type
     auto store_act = [&](long idx, const f4& y) __attribute__((always_inline)) {
         if constexpr (DT == DT_F32 || DT == DT_F32X) {
             *reinterpret_cast<f4*>(static_cast<float*>(a.out) + idx) = y;
-        } else if (DT == DT_FP8 && !a.out_bf16) {
-            const float q = a.out_q;
+        } else if ((DT == DT_FP8 && !a.out_bf16) || (DT == DT_BF16 && a.out_e4m3)) {
+            const f4 v = a.out_q * y;
+            count_sat(v);
             *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
-                e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
-        } else if (DT == DT_BF16 && a.out_e4m3) {
-            const float q = a.out_q;
-            *reinterpret_cast<uint32_t*>(static_cast<uint8_t*>(a.out) + idx) =
-                e4m3x2(q * y[0], q * y[1]) | (e4m3x2(q * y[2], q * y[3]) << 16);
+                e4m3x2(v[0], v[1]) | (e4m3x2(v[2], v[3]) << 16);
         } else {
             bf16x4 h;
 #pragma unroll

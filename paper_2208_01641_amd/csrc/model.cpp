@@ -252,9 +252,101 @@ struct Spec {
 
 }  // namespace
 
+int Codec::upload_rscale(LayerGPU& L)
+{
+    std::vector<float> rs(L.wsc.size());
+    for (size_t r = 0; r < rs.size(); ++r) rs[r] = L.wsc[r] * L.in_scale;
+    HIP_TRY(hipMemcpy(L.d_rscale, rs.data(), rs.size() * sizeof(float), hipMemcpyHostToDevice));
+    return LIC_OK;
+}
+
+// Activation scales of the e4m3 form: each layer that stores e4m3
+// activations gets q = 448 / (2 amax), amax the largest |value| it produces
+// on the calibration frames (one binary order of headroom), with the scales
+// of the layers before it already in place; the layer that reads its output
+// undoes q in its epilogue.  The layers run once with bf16 outputs to
+// measure amax and once more in e4m3 to feed the next layer.
+int Codec::calibrate_fp8(const float* x, int n, int H, int W)
+{
+    if (cfg.precision != LIC_PREC_FP8) return LIC_OK;
+    const FrameDims d(H, W);
+    size_t cap = 0;
+    for (int id : {LIC_GA0, LIC_GA1, LIC_GA2, LIC_GA3, LIC_GS0, LIC_GS1, LIC_GS2}) {
+        size_t bi, bo, ba;
+        layer_bytes(id, n, d, &bi, &bo, &ba);
+        cap = std::max(cap, std::max(bi, std::max(bo, ba)) * 4);     // room for any storage type
+    }
+    // buf[0]: measured (bf16) outputs; buf[1], buf[2]: e4m3 activations; buf[3]: symbols of y
+    void* buf[4] = {nullptr, nullptr, nullptr, nullptr};
+    for (void*& b : buf)
+        if (hipMalloc(&b, cap) != hipSuccess) {
+            for (void* q : buf) (void)hipFree(q);
+            err = "calibration buffers: device allocation failed";
+            return LIC_E_NOMEM;
+        }
+    std::vector<uint16_t> host(cap / 2);
+    std::string e;
+    int rc = LIC_OK;
+    // amax of layer id's output (bf16 storage) on input `in`
+    auto measure = [&](int id, const void* in, float* amax) -> int {
+        LayerGPU& L = layers[id];
+        const bool e8 = L.out_e4m3, b16 = L.out_bf16;
+        if (L.dt == DT_BF16) L.out_e4m3 = false; else L.out_bf16 = true;
+        size_t bi, bo, ba;
+        layer_bytes(id, n, d, &bi, &bo, &ba);
+        int r = launch_layer(id, n, d, in, buf[0], nullptr, layer_stream, &e);
+        L.out_e4m3 = e8;
+        L.out_bf16 = b16;
+        if (r != LIC_OK) { err = e; return r; }
+        if (hipMemcpyAsync(host.data(), buf[0], bo, hipMemcpyDeviceToHost, layer_stream) != hipSuccess ||
+            hipStreamSynchronize(layer_stream) != hipSuccess) { err = "calibration copy failed"; return LIC_E_HIP; }
+        float m = 0.0f;
+        for (size_t i = 0; i < bo / 2; ++i) {
+            const uint32_t u = (uint32_t)host[i] << 16;
+            float v;
+            memcpy(&v, &u, 4);
+            m = std::max(m, std::fabs(v));
+        }
+        *amax = m;
+        return LIC_OK;
+    };
+    // sets layer id's scale from its output on `in`, runs it in e4m3 into out
+    auto step = [&](int id, const void* in, void* out, void* aux) -> int {
+        float amax = 0.0f;
+        int r = measure(id, in, &amax);
+        if (r != LIC_OK) return r;
+        LayerGPU& L = layers[id];
+        if (L.dt == DT_FP8 ? !L.out_bf16 : L.out_e4m3) {
+            L.out_q = amax > 0.0f && std::isfinite(amax) ? 448.0f / (2.0f * amax) : kActQ;
+            LayerGPU& next = layers[id + 1];
+            next.in_scale = 1.0f / L.out_q;
+            if ((r = upload_rscale(next)) != LIC_OK) return r;
+        }
+        if ((r = launch_layer(id, n, d, in, out, aux, layer_stream, &e)) != LIC_OK) { err = e; return r; }
+        return LIC_OK;
+    };
+    if ((rc = step(LIC_GA0, x, buf[1], nullptr)) == LIC_OK && (rc = step(LIC_GA1, buf[1], buf[2], nullptr)) == LIC_OK &&
+        (rc = step(LIC_GA2, buf[2], buf[1], nullptr)) == LIC_OK &&
+        (rc = launch_layer(LIC_GA3, n, d, buf[1], buf[2], buf[3], layer_stream, &e)) == LIC_OK &&
+        (rc = step(LIC_GS0, buf[3], buf[1], nullptr)) == LIC_OK)
+        rc = step(LIC_GS1, buf[1], buf[2], nullptr);
+    if (rc != LIC_OK && err.empty()) err = e;
+    if (hipStreamSynchronize(layer_stream) != hipSuccess && rc == LIC_OK) { err = "calibration failed"; rc = LIC_E_HIP; }
+    for (void* b : buf) (void)hipFree(b);
+    // captured serving graphs hold the old scales in their kernel arguments
+    server_drop_graphs(ST_GPU_ENC);
+    server_drop_graphs(ST_GPU_GS);
+    return rc;
+}
+
 int Codec::build_layers(const ParamMap& P)
 {
     HIP_TRY(hipSetDevice(cfg.hip_device));
+    if (cfg.precision == LIC_PREC_FP8) {
+        d_sat = (unsigned long long*)dev_alloc(sizeof(unsigned long long));
+        if (!d_sat) { err = "device allocation failed"; return LIC_E_NOMEM; }
+        HIP_TRY(hipMemset(d_sat, 0, sizeof(unsigned long long)));
+    }
     const int C = kind == 0 ? M : N;
     d_medians = (float*)dev_alloc(sizeof(float) * 512);
     d_zero = (float*)dev_alloc(sizeof(float) * 512);
@@ -368,12 +460,12 @@ int Codec::build_layers(const ParamMap& P)
                 const size_t end = i + 1 < ph.size() ? pm.off[i + 1] : total;
                 for (size_t j = pm.off[i]; j < end; ++j) h8[j] = e4m3_rne(wp[j] / wsc[((j - pm.off[i]) / cin) % (size_t)L.cop]);
             }
-            const float in_scale = (sp.ld == LD_F32) ? 1.0f / kActQ : 1.0f;
-            std::vector<float> rs(L.cop);
-            for (int r = 0; r < L.cop; ++r) rs[r] = wsc[r] * in_scale;
+            L.in_scale = (sp.ld == LD_F32) ? 1.0f / kActQ : 1.0f;
+            L.wsc = wsc;
             L.d_rscale = (float*)dev_alloc(L.cop * sizeof(float));
             if (!L.d_rscale) { err = "device allocation failed"; return LIC_E_NOMEM; }
-            HIP_TRY(hipMemcpy(L.d_rscale, rs.data(), L.cop * sizeof(float), hipMemcpyHostToDevice));
+            const int rc = upload_rscale(L);
+            if (rc != LIC_OK) return rc;
             HIP_TRY(hipMemcpy(L.d_w, h8.data(), total, hipMemcpyHostToDevice));
         } else {
             HIP_TRY(hipMemcpy(L.d_w, wp.data(), total * esz, hipMemcpyHostToDevice));
@@ -540,7 +632,8 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.kk = L.k;
     a.pad = L.k / 2;
     a.rscale = L.d_rscale;
-    a.out_q = kActQ;
+    a.out_q = L.out_q;
+    a.sat = d_sat;
     a.out_e4m3 = L.out_e4m3 ? 1 : 0;
     a.out_bf16 = L.out_bf16 ? 1 : 0;
 
