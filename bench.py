@@ -667,6 +667,18 @@ def main():
         var["serving_load_sweep_bf16"] = [_round(run_serving(precision=1, threads=threads, rate=rate,
                                                              duration_s=4.0, warmup_s=1.0))
                                           for rate in (60.0, 120.0, 180.0)]
+        # the streaming sample application: sender and receiver processes over
+        # TCP on this host, factorized prior at 720p, paced at 30 frames/s and
+        # unpaced (8 frames per codec call)
+        from paper_2208_01641_amd import stream
+        for name, fps, n, chunk in (("stream_720p30_factorized_tcp", 30.0, 120, 1),
+                                    ("stream_720p_factorized_tcp_unpaced", 0.0, 320, 8)):
+            r = stream.run_loopback(frames=n, fps=fps, kind=0, chunk=chunk, lanes=RANS_LANES, timeout_s=240)
+            rv = r["received"]
+            assert rv["frames"] == n and rv["bitstream_sha16"] == r["sent"]["bitstream_sha16"]
+            var[name] = _round({"frames": n, "fps": rv["fps"], "latency_p50_ms": rv["latency_p50_ms"],
+                                "latency_p99_ms": rv["latency_p99_ms"], "bytes_per_frame": r["sent"]["bytes"] / n})
+            progress(f"{name}: {rv['fps']:.1f} frames/s")
         if args.distill_pairs > 0:
             var["distilled_gs"] = run_distilled(pairs=args.distill_pairs, steps=args.distill_steps, threads=threads)
         res["variants"] = var

@@ -13,6 +13,15 @@ LIB_PATH = os.path.join(_HERE, "liblic.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError("liblic.so is not built: run `python paper_2208_01641_amd/build.py` (HIP library for gfx950)")
 
+# One HIP runtime per process: PyTorch's wheel carries its own HIP runtime,
+# which the library's libamdhip64.so.7 dependency resolves to once torch is
+# loaded.  Loaded the other way round, the process would hold two runtimes and
+# the second to start would find no device.
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 lib = ctypes.CDLL(LIB_PATH)
 
 c_int, c_long, c_size_t, c_void_p, c_uint32, c_double = (ctypes.c_int, ctypes.c_long, ctypes.c_size_t,
