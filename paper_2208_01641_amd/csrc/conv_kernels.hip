@@ -1247,10 +1247,18 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         const float* __restrict__ thr = a.thr;
         // idx = #{k < 63 : thr[k] < s} with s = v (thr holds ln t_k: exp(v) >
         // t_k <=> v > ln t_k) or s = max(v, 0, t_0) (thr holds t_k).  The
-        // thresholds are the same for every lane: they are read as scalars, 16
-        // at a time, and counted against every element of the tile (a
-        // per-lane search would gather them).
-        float sv[MT][NT][4];
+        // table is log-spaced, so (s - thr[0]) / step (ReLU: log2(s / thr[0])
+        // / step) is within a step or two of the count; from there the count
+        // is settled by comparisons with the table itself (staged per wave in
+        // LDS), so the result is exactly the count whatever the first guess.
+        __shared__ float thr_s[PIXW][64];
+        float* const ts = thr_s[wave / KSPLIT];
+        ts[lane] = lane < 63 ? thr[lane] : __builtin_inff();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float t0 = thr[0];
+        const float inv = a.hs_exp ? 62.0f / (thr[62] - t0) : 62.0f / __log2f(thr[62] / t0);
         int cnt[MT][NT][4];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -1259,25 +1267,13 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
                     const float y = acc[mt][nt][i];
-                    sv[mt][nt][i] = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), thr[0]);
-                    cnt[mt][nt][i] = 0;
+                    const float s = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), t0);
+                    const float u = a.hs_exp ? (s - t0) * inv : __log2f(s / t0) * inv;
+                    int e = (int)ceilf(fminf(fmaxf(u, 0.0f), 63.0f));     // NaN: 0
+                    while (e < 63 && ts[e] < s) ++e;
+                    while (e > 0 && !(ts[e - 1] < s)) --e;
+                    cnt[mt][nt][i] = e;
                 }
-#pragma unroll 1
-        for (int k0 = 0; k0 < 64; k0 += 16) {
-            float t[16];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) t[j] = thr[k0 + j < 63 ? k0 + j : 62];
-#pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const bool real = k0 + j < 63;              // 63 thresholds
-#pragma unroll
-                for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-                    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) cnt[mt][nt][i] += (real && t[j] < sv[mt][nt][i]) ? 1 : 0;
-            }
-        }
         uint32_t pk[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
