@@ -65,9 +65,10 @@ def kernel_src_hash():
         return hashlib.sha256(fh.read()).hexdigest()[:16]
 
 
-def traffic_for(layer):
-    """HBM bytes per launch from the committed rocprofv3 counter summary,
-    or None if there is none or the kernel source changed since."""
+def traffic_for(layer, precision):
+    """HBM bytes per launch (one 720p frame) of a layer of the codec in a
+    precision form (fp32, bf16, fp8) from the committed rocprofv3 counter
+    summary, or None if there is none or the kernel source changed since."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -75,7 +76,7 @@ def traffic_for(layer):
         return None
     if t.get("kernel_src_sha256_16") != kernel_src_hash():
         return None
-    ent = t.get("layers", {}).get(layer)
+    ent = t.get("forms", {}).get(precision, {}).get(layer)
     return None if ent is None else ent.get("bytes_per_launch")
 
 
@@ -548,7 +549,8 @@ def main():
     peak = round(PEAK_TFLOPS[form], 2)
     ach = per_layer[dom]["tflops"]
     roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
-                "frac": round(ach / peak, 4), "traffic": traffic_for(dom) if not prec else None,
+                "frac": round(ach / peak, 4),
+                "traffic": traffic_for(dom, args.precision) if (H, W, N, M) == (720, 1280, 128, 192) else None,
                 "kernel": dom, "form": form, "peak_basis": PEAK_BASIS[form],
                 "avg_us": round(per_layer[dom]["avg_us"], 2),
                 "flops_per_launch": per_layer[dom]["flops_per_launch"]}
