@@ -13,7 +13,11 @@ loops); this module strings them together into the codecs of the paper:
     a per-channel offset -> entropy code with per-channel tables;
   * scale hyperprior (Section III.B, Fig. 1): additionally z = h_a(|y|) is
     quantised and coded, and h_s(z_hat) gives the scales whose table index
-    selects the Gaussian table each element of y is coded with.
+    selects the Gaussian table each element of y is coded with;
+  * context model with parallel context prediction (the class of codecs that
+    Sections II and VII name as the next step): a mean-scale hyperprior whose
+    entropy parameters also see a context of already decoded latents, in the
+    two-pass checkerboard order, so that each pass is one parallel step.
 
 The architecture details the paper leaves to its cited models (layer shapes,
 GDN, quantiser, tables, rANS, bitstream) follow the readings listed in the
@@ -387,6 +391,75 @@ def fnv1a32(data: bytes) -> int:
 # ----------------------------------------------------------------------------
 # the codec
 # ----------------------------------------------------------------------------
+# ----------------------------------------------------------------------------
+# context model with checkerboard-parallel prediction (kind 2)
+# ----------------------------------------------------------------------------
+def checkerboard(Hy: int, Wy: int) -> np.ndarray:
+    """Anchor positions of the two-pass order: (r + c) even.  Anchors get
+    their entropy parameters from the hyperprior alone; the other half also
+    from a context of the anchors."""
+    r = np.arange(Hy)[:, None]
+    c = np.arange(Wy)[None, :]
+    return (r + c) % 2 == 0
+
+
+def context_mask(k: int = 5) -> np.ndarray:
+    """Taps of the k x k context kernel: offsets (dy, dx) with dy + dx odd.
+    Seen from a non-anchor these are exactly the anchors of the window."""
+    d = np.arange(k) - k // 2
+    return (d[:, None] + d[None, :]) % 2 != 0
+
+
+def context(yhat, w, b) -> np.ndarray:
+    """Context of the non-anchors: a k x k convolution (stride 1, zero
+    padding k // 2) with the masked kernel over y_hat with every non-anchor
+    set to zero, plus bias; zero at the anchors (their context is empty)."""
+    yhat = np.asarray(yhat, np.float64)
+    C, Hy, Wy = yhat.shape
+    A = checkerboard(Hy, Wy)[None]
+    k = w.shape[-1]
+    wm = np.asarray(w, np.float64) * context_mask(k)[None, None]
+    out = conv2d(np.where(A, yhat, 0.0), wm, b, 1, k // 2)
+    return np.where(A, 0.0, out)
+
+
+def conv1x1(x, w, b) -> np.ndarray:
+    """1 x 1 convolution: one matrix product over all positions."""
+    x = np.asarray(x, np.float64)
+    C, H, W = x.shape
+    w2 = np.asarray(w, np.float64).reshape(w.shape[0], C)
+    return (w2 @ x.reshape(C, H * W)).reshape(-1, H, W) + np.asarray(b, np.float64)[:, None, None]
+
+
+def entropy_parameters(P, psi, ctx):
+    """Mean and pre-activation scale of every latent element from the
+    concatenation [psi; ctx]: 1 x 1 layers with ReLU between them.  The
+    first M output channels are the means, the last M the scales."""
+    h = relu(conv1x1(np.concatenate([psi, ctx]), P["ep0.w"], P["ep0.b"]))
+    h = relu(conv1x1(h, P["ep1.w"], P["ep1.b"]))
+    out = conv1x1(h, P["ep2.w"], P["ep2.b"])
+    M = out.shape[0] // 2
+    return out[:M], out[M:]
+
+
+def checkerboard_take(hwc, part: int) -> np.ndarray:
+    """Hy x Wy/2 x C: row by row, the positions of the anchors (part 0) or of
+    the other half (part 1) in increasing column order."""
+    Hy, Wy = hwc.shape[:2]
+    A = checkerboard(Hy, Wy)
+    sel = A if part == 0 else ~A
+    return np.stack([hwc[r][sel[r]] for r in range(Hy)])
+
+
+def checkerboard_put(hwc, part: int, vals) -> None:
+    """Inverse of checkerboard_take: writes vals into the positions of the set."""
+    Hy, Wy = hwc.shape[:2]
+    A = checkerboard(Hy, Wy)
+    sel = A if part == 0 else ~A
+    for r in range(Hy):
+        hwc[r][sel[r]] = vals[r]
+
+
 def pad64(x):
     """Zero-pad a C x H x W image at the bottom and right to multiples of 64."""
     C, H, W = x.shape
@@ -399,7 +472,8 @@ def pad64(x):
 class Model:
     """Parameters of one codec plus the entropy tables derived from them.
 
-    kind 0 = factorized prior, 1 = scale hyperprior.  hs_out selects the
+    kind 0 = factorized prior, 1 = scale hyperprior, 2 = mean-scale
+    hyperprior with a checkerboard context model.  hs_out selects the
     output activation of h_s (1 = exp, 0 = ReLU); norm the normalisation of
     g_a / g_s (0 = GDN / IGDN, 1 = 1DN and its inverse); lanes the entropy
     coder (0 = byte-wise rANS, K = interleaved word-wise rANS with K states).
@@ -445,7 +519,8 @@ class Model:
 
     def h_a(self, y, keep=None):
         P = self.P
-        h = relu(conv2d(np.abs(y), P["ha0.w"], P["ha0.b"], 1, 1))
+        # the scale hyperprior sees |y|; the mean-scale model needs the signs
+        h = relu(conv2d(np.abs(y) if self.kind == 1 else y, P["ha0.w"], P["ha0.b"], 1, 1))
         if keep is not None: keep.append(h)
         h = relu(conv2d(h, P["ha1.w"], P["ha1.b"], 2, 2))
         if keep is not None: keep.append(h)
@@ -454,7 +529,9 @@ class Model:
         return h
 
     def h_s(self, zhat, keep=None):
-        """Pre-activation output v of h_s; scales = exp(v) or ReLU(v)."""
+        """Pre-activation output v of h_s; scales = exp(v) or ReLU(v).  For
+        the context model (kind 2) the 2M channels psi that feed the
+        entropy-parameter layers."""
         P = self.P
         h = relu(deconv2d(zhat, P["hs0.w"], P["hs0.b"], 2, 2, 1))
         if keep is not None: keep.append(h)
@@ -463,6 +540,51 @@ class Model:
         h = conv2d(h, P["hs2.w"], P["hs2.b"], 1, 1)
         if keep is not None: keep.append(h)
         return h
+
+    # ---- context model (kind 2): the two checkerboard passes ----
+    def checkerboard_passes(self, psi, y=None, decode_set=None, keep=None):
+        """Entropy parameters, symbols and y_hat of the context model.
+
+        Pass 1 (anchors, (r + c) even): mean and scale from psi alone (zero
+        context).  The anchors are then quantised (encoder, from y) or decoded
+        (decoder, decode_set(0, idx)), giving y_hat at the anchors.  Pass 2
+        (the other half): the context of the anchors' y_hat joins psi.  A
+        decoder thus repeats the encoder's computation exactly: pass 1 needs
+        only z_hat, pass 2 only z_hat and the anchors.  Returns a dict of
+        M x Hy x Wy arrays mu, sraw (pre-activation scale), idx, sym, yhat."""
+        P = self.P
+        M2, Hy, Wy = psi.shape
+        M = M2 // 2
+        A = checkerboard(Hy, Wy)[None]
+        mu1, s1 = entropy_parameters(P, psi, np.zeros_like(psi))
+        idx1 = scale_index(scales_from_hs(s1, self.hs_out), self.t)
+        if y is not None:
+            sym1, _ = quantize(y, mu1)
+        else:
+            sym1 = decode_set(0, idx1)
+        yhat1 = np.where(A, sym1 + mu1, 0.0)
+        ctx = context(yhat1, P["cx.w"], P["cx.b"])
+        mu2, s2 = entropy_parameters(P, psi, ctx)
+        idx2 = scale_index(scales_from_hs(s2, self.hs_out), self.t)
+        if y is not None:
+            sym2, _ = quantize(y, mu2)
+        else:
+            sym2 = decode_set(1, idx2)
+        r = {"mu": np.where(A, mu1, mu2), "sraw": np.where(A, s1, s2), "idx": np.where(A, idx1, idx2),
+             "sym": np.where(A, sym1, sym2).astype(np.int32), "ctx": ctx}
+        r["yhat"] = r["sym"] + r["mu"]
+        return r
+
+    def _code_sets(self, sym, idx, S):
+        """rANS streams of the anchors, then of the other half: S row slices
+        each, positions of the set in raster order, channels fastest."""
+        M, Hy, Wy = sym.shape
+        out = []
+        for part in (0, 1):
+            ys = checkerboard_take(np.transpose(sym, (1, 2, 0)), part).reshape(Hy, -1) - SYM_MIN
+            yt = checkerboard_take(np.transpose(idx, (1, 2, 0)), part).reshape(Hy, -1)
+            out += [self._enc(ys[a:b], yt[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+        return out
 
     # ---- entropy coding helpers (HWC raster, channel fastest) ----
     @staticmethod
@@ -516,20 +638,29 @@ class Model:
             with T("h_s"):
                 v = self.h_s(zhat, inter.setdefault("hs", []))
             inter["v"] = v
-            idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+            if self.kind == 1:
+                idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+                sym_y, yhat = quantize(y, 0.0)
+            else:
+                with T("context"):
+                    cp = self.checkerboard_passes(v, y=y)
+                inter.update(mu=cp["mu"], sraw=cp["sraw"], ctx=cp["ctx"])
+                idx, sym_y, yhat = cp["idx"], cp["sym"], cp["yhat"]
             inter["idx"] = idx
-            sym_y, yhat = quantize(y, 0.0)
             inter["sym_y"] = sym_y
             with T("rans_z"):
                 zs, zt = self._code_factorized(sym_z)
                 payloads.append(self._enc(zs, zt, self.freq_fact))
             with T("rans_y"):
-                ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
-                ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
-                ys = [self._enc(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+                if self.kind == 1:
+                    ysym = (np.transpose(sym_y, (1, 2, 0)) - SYM_MIN).reshape(Hy, Wy * M)
+                    ytab = np.transpose(idx, (1, 2, 0)).reshape(Hy, Wy * M)
+                    ys = [self._enc(ysym[a:b], ytab[a:b], self.freq_gauss) for a, b in self.slice_rows(Hy, S)]
+                else:
+                    ys = self._code_sets(sym_y, idx, S)
         inter["yhat"] = yhat
         bits = pack_container(self.kind, self.hs_out, S, H, W, self.N, self.M, self.model_id,
-                              payloads[0] if self.kind == 1 else None, ys, norm=self.norm, lanes=self.lanes)
+                              payloads[0] if self.kind else None, ys, norm=self.norm, lanes=self.lanes)
         return bits, inter
 
     def decode(self, bits: bytes, keep=None, times=None):
@@ -549,6 +680,7 @@ class Model:
                     tab = np.broadcast_to(np.arange(M, dtype=np.int32), (b - a, Wy, M))
                     sym = self._dec(data, tab, self.freq_fact, (b - a) * Wy * M).reshape(b - a, Wy, M)
                     yhat_hwc[a:b] = sym + SYM_MIN + self.medians[None, None, :].astype(np.float64)
+            yhat = np.transpose(yhat_hwc, (2, 0, 1))
         else:
             Hz, Wz = Hy // 4, Wy // 4
             with T("rans_z"):
@@ -558,15 +690,31 @@ class Model:
             inter["sym_z"] = np.transpose(sz, (2, 0, 1))
             with T("h_s"):
                 v = self.h_s(zhat)
-            idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+            if self.kind == 1:
+                idx = scale_index(scales_from_hs(v, self.hs_out), self.t)
+                idx_hwc = np.transpose(idx, (1, 2, 0))
+                yhat_hwc = np.empty((Hy, Wy, M), np.float64)
+                with T("rans_y"):
+                    for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
+                        sym = self._dec(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
+                        yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
+                yhat = np.transpose(yhat_hwc, (2, 0, 1))
+            else:
+                def decode_set(part, idx_chw):
+                    tab = checkerboard_take(np.transpose(idx_chw, (1, 2, 0)), part)       # Hy x Wy/2 x M
+                    got = np.empty(tab.shape, np.int32)
+                    for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"][part * S:(part + 1) * S]):
+                        got[a:b] = self._dec(data, tab[a:b], self.freq_gauss, tab[a:b].size).reshape(
+                            tab[a:b].shape) + SYM_MIN
+                    out = np.zeros((Hy, Wy, M), np.int32)
+                    checkerboard_put(out, part, got)
+                    return np.transpose(out, (2, 0, 1))
+
+                with T("context"):
+                    cp = self.checkerboard_passes(v, decode_set=decode_set)
+                idx, yhat = cp["idx"], cp["yhat"]
+                inter.update(mu=cp["mu"], sym_y=cp["sym"])
             inter["idx"] = idx
-            idx_hwc = np.transpose(idx, (1, 2, 0))
-            yhat_hwc = np.empty((Hy, Wy, M), np.float64)
-            with T("rans_y"):
-                for (a, b), data in zip(self.slice_rows(Hy, S), hdr["y"]):
-                    sym = self._dec(data, idx_hwc[a:b], self.freq_gauss, (b - a) * Wy * M)
-                    yhat_hwc[a:b] = sym.reshape(b - a, Wy, M) + SYM_MIN
-        yhat = np.transpose(yhat_hwc, (2, 0, 1))
         inter["yhat"] = yhat
         with T("g_s"):
             xr = self.g_s(yhat)
@@ -597,6 +745,8 @@ class _Stages:
 # output of h_s, bit 1 = 1DN, bits 2..4 = log2 of the interleaved rANS
 # states, 0 for the byte-wise coder), u8 S, u16 H, u16 W, u16 N, u16 M, u32 model id,
 # [u32 len_z], S x u32 len_y, payloads z, y_0 .. y_{S-1}; little-endian.
+# The context model (kind 2) has 2S y payloads: the S row slices of the
+# anchors, then the S row slices of the other half.
 # ----------------------------------------------------------------------------
 def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys, norm: int = 0, lanes: int = 0) -> bytes:
     """flags: bit 0 = exp output of h_s, bit 1 = 1DN instead of GDN, bits 2..4
@@ -606,10 +756,11 @@ def pack_container(kind, hs_out, S, H, W, N, M, model_id, z, ys, norm: int = 0, 
     out = bytearray(b"LICS")
     out += struct.pack("<BBBBHHHHI", 1, kind, (hs_out & 1) | ((norm & 1) << 1) | (lg << 2), S, H, W, N, M,
                        model_id)
-    if kind == 1:
+    assert len(ys) == (2 * S if kind == 2 else S)
+    if kind:
         out += struct.pack("<I", len(z))
-    out += struct.pack(f"<{S}I", *[len(y) for y in ys])
-    if kind == 1:
+    out += struct.pack(f"<{len(ys)}I", *[len(y) for y in ys])
+    if kind:
         out += z
     for y in ys:
         out += y
@@ -620,10 +771,10 @@ def parse_container(bits: bytes) -> dict:
     if len(bits) < 20 or bits[:4] != b"LICS":
         raise ValueError("not a LICS bitstream")
     ver, kind, flags, S, H, W, N, M, mid = struct.unpack_from("<BBBBHHHHI", bits, 4)
-    if ver != 1 or kind not in (0, 1) or S < 1 or H == 0 or W == 0 or flags >> 5 or ((flags >> 2) & 7) > 5:
+    if ver != 1 or kind not in (0, 1, 2) or S < 1 or H == 0 or W == 0 or flags >> 5 or ((flags >> 2) & 7) > 5:
         raise ValueError("bad header")
     pos = 20
-    nlen = S + (1 if kind == 1 else 0)
+    nlen = (2 * S if kind == 2 else S) + (1 if kind else 0)
     if len(bits) < pos + 4 * nlen:
         raise ValueError("truncated header")
     lens = struct.unpack_from(f"<{nlen}I", bits, pos)
@@ -633,7 +784,7 @@ def parse_container(bits: bytes) -> dict:
     lg = (flags >> 2) & 7
     hdr = {"kind": kind, "hs_out": flags & 1, "norm": (flags >> 1) & 1, "lanes": (1 << lg) if lg else 0, "S": S,
            "H": H, "W": W, "N": N, "M": M, "model_id": mid}
-    if kind == 1:
+    if kind:
         hdr["z"] = bits[pos:pos + lens[0]]
         pos += lens[0]
         lens = lens[1:]

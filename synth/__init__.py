@@ -148,8 +148,22 @@ def layer_specs(kind: int, N: int, M: int):
     ha = [("ha0", "conv", M, N, 3, "relu"), ("ha1", "conv", N, N, 5, "relu"),
           ("ha2", "conv", N, N, 5, "")]
     hs = [("hs0", "deconv", N, N, 5, "relu"), ("hs1", "deconv", N, N, 5, "relu"),
-          ("hs2", "conv", N, M, 3, "")]
-    return ga + gs + ha + hs
+          ("hs2", "conv", N, M if kind == 1 else 2 * M, 3, "")]
+    if kind == 1:
+        return ga + gs + ha + hs
+    # kind 2: context model with checkerboard-parallel prediction; cx is the
+    # 5x5 context convolution (its checkerboard mask is applied by the user
+    # of the weights, not stored), ep0..ep2 the 1x1 entropy-parameter layers
+    E1, E2 = context_widths(M)
+    ctx = [("cx", "conv", M, 2 * M, 5, ""), ("ep0", "conv", 4 * M, E1, 1, "relu"),
+           ("ep1", "conv", E1, E2, 1, "relu"), ("ep2", "conv", E2, 2 * M, 1, "")]
+    return ga + gs + ha + hs + ctx
+
+
+def context_widths(M: int):
+    """Hidden widths of the entropy-parameter layers of the context model:
+    about 10 M / 3 and 8 M / 3, in multiples of 32 (640 and 512 for M = 192)."""
+    return 32 * round(10 * M / 96), 32 * round(8 * M / 96)
 
 
 def model_params(kind: int, N: int, M: int, seed: int = WEIGHT_SEED,
@@ -169,7 +183,8 @@ def model_params(kind: int, N: int, M: int, seed: int = WEIGHT_SEED,
     P: "OrderedDict[str, np.ndarray]" = OrderedDict()
     for name, op, cin, cout, k, post in layer_specs(kind, N, M):
         shape = (cout, cin, k, k) if op == "conv" else (cin, cout, k, k)
-        std = math.sqrt(2.0 / (cin * k * k))
+        # fan-in of the context convolution: the 12 taps its mask keeps
+        std = math.sqrt(2.0 / (cin * (12 if name == "cx" else k * k)))
         P[name + ".w"] = (rng.standard_normal(shape) * std).astype(np.float32)
         P[name + ".b"] = rng.uniform(-0.05, 0.05, cout).astype(np.float32)
         if post in ("gdn", "igdn"):
