@@ -49,7 +49,8 @@ typedef enum {
     LIC_E_MODEL = -8      /* weight blob or bitstream belongs to another model    */
 } lic_status;
 
-enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1 };
+enum { LIC_KIND_FACTORIZED = 0, LIC_KIND_HYPERPRIOR = 1,
+       LIC_KIND_CONTEXT = 2 };  /* mean-scale hyperprior with a checkerboard context model */
 enum { LIC_PREC_FP32 = 0, LIC_PREC_BF16 = 1, LIC_PREC_FP8 = 2 };
 enum { LIC_HS_RELU = 0, LIC_HS_EXP = 1 };
 enum { LIC_NORM_GDN = 0, LIC_NORM_1DN = 1 };
@@ -57,7 +58,14 @@ enum { LIC_NORM_GDN = 0, LIC_NORM_1DN = 1 };
 /* Creation parameters.  Fill with codec_default_config() first. */
 typedef struct {
     uint32_t struct_size;      /* sizeof(codec_config), for ABI versioning           */
-    int32_t  kind;             /* LIC_KIND_*: factorized prior [1] or hyperprior [2] */
+    int32_t  kind;             /* LIC_KIND_*: factorized prior [1], hyperprior [2],  */
+                               /* or the context model: a mean-scale hyperprior      */
+                               /* whose entropy parameters also see a context of     */
+                               /* decoded latents, in two parallel checkerboard      */
+                               /* passes (the parallel context prediction Sections   */
+                               /* II and VII point to; N=128 M=192, FP32 or BF16     */
+                               /* form, full g_s, no serving; its h_a / h_s, context */
+                               /* and entropy-parameter layers run in FP32)          */
     int32_t  N, M;             /* transform / latent channels (128/192 or 192/320)   */
     int32_t  precision;        /* LIC_PREC_FP32, _BF16 or _FP8: g_a / g_s GEMM       */
                                /* operands and their activations in bf16, or in OCP  */
@@ -206,12 +214,35 @@ int codec_poll(codec_t* c, lic_result* done, int max, int timeout_us);
 /*  LIC_GS3        NHWC f32                    image NCHW f32 (cropped,      */
 /*                                             clamped)           pre-clamp   */
 /*                                             image n x 3 x Hp x Wp / NULL   */
+/*                                                                          */
+/*  Context model (kind 2; every tensor on the Hy x Wy latent grid, f32):   */
+/*  HA0 takes y itself; HS2 writes psi (2M channels) into channels [0, 2M)  */
+/*  of Z = [psi; ctx] (4M channels); GS0 takes y_hat (f32, bf16 in the BF16  */
+/*  form).  The anchors are the positions with (row + column) even; the     */
+/*  *A layers run at the anchors, the *N layers at the other positions.     */
+/*  LIC_CX         y_hat NHWC (anchors read)   Z, channels [2M, 4M) at the   */
+/*                                             non-anchors (checkerboard-    */
+/*                                             masked 5x5 convolution)        */
+/*  LIC_EP0A/N     Z                           h1 NHWC (640 ch)   -           */
+/*  LIC_EP1A/N     h1                          h2 NHWC (512 ch)   -           */
+/*  LIC_EP2A/N     h2                          idx uint8          sym int8 /  */
+/*                                                                NULL        */
+/*    with codec_run_layer_ex: in2 = y (encoder) or NULL (decoder); out2 =  */
+/*    y_hat = sym + mean on the full grid (encoder) or the means (decoder). */
+/*    idx, sym and the decoder's means are checkerboard-major: [n][part]    */
+/*    [Hy][Wy/2][M], part 0 the anchors, entry j of row r at column         */
+/*    2j + ((r + part) & 1).  The anchors' ctx channels of Z must be zero   */
+/*    (the codec clears them; a caller of EP0A does).                       */
 /* ------------------------------------------------------------------------ */
 enum {
     LIC_GA0 = 0, LIC_GA1, LIC_GA2, LIC_GA3,
     LIC_HA0, LIC_HA1, LIC_HA2,
     LIC_HS0, LIC_HS1, LIC_HS2,
     LIC_GS0, LIC_GS1, LIC_GS2, LIC_GS3,
+    /* context model (kind 2) */
+    LIC_CX,                           /* context convolution of the non-anchors */
+    LIC_EP0A, LIC_EP1A, LIC_EP2A,     /* entropy parameters, anchor pass */
+    LIC_EP0N, LIC_EP1N, LIC_EP2N,     /* entropy parameters, second pass */
     LIC_NUM_LAYERS
 };
 /* Loads the distilled synthesis transform used by the decoder when gs_mode
@@ -243,6 +274,10 @@ int codec_fp8_scales(const codec_t* c, float* q, int max, unsigned long long* sa
 
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W,
                     const void* in, void* out, void* aux);
+/* The same with the second input and output of LIC_EP2A / LIC_EP2N (see the
+ * table above); other layers ignore in2 and out2. */
+int codec_run_layer_ex(codec_t* c, int layer, int n, int H, int W, const void* in, void* out, void* aux,
+                       const void* in2, void* out2);
 /* Bytes codec_run_layer reads from in and writes to out / aux for n frames
  * of H x W in this codec's form (0: the layer takes no such buffer; aux is
  * optional where the table above says so).  Element sizes: images, y, z,

@@ -96,6 +96,7 @@ SIGNATURES = {
     "codec_destroy": (None, [P]),
     "codec_last_error": (ctypes.c_char_p, [P]),
     "codec_run_layer": (c_int, [P, c_int, c_int, c_int, c_int, P, P, P]),
+    "codec_run_layer_ex": (c_int, [P, c_int, c_int, c_int, c_int, P, P, P, P, P]),
     "codec_tables": (c_long, [P, c_int, P, c_size_t]),
     "codec_time_layers": (c_int, [P, c_uint32]),
     "codec_layer_kernel": (c_int, [P, c_int, c_int, c_int, P, P]),
@@ -141,5 +142,6 @@ LIC_OK, LIC_E_ARG, LIC_E_NOMEM, LIC_E_HIP, LIC_E_CORRUPT, LIC_E_SMALLBUF, LIC_E_
     0, -1, -2, -3, -4, -5, -6, -7, -8
 STATUS_NAMES = {0: "LIC_OK", -1: "LIC_E_ARG", -2: "LIC_E_NOMEM", -3: "LIC_E_HIP", -4: "LIC_E_CORRUPT",
                 -5: "LIC_E_SMALLBUF", -6: "LIC_E_BUDGET", -7: "LIC_E_STATE", -8: "LIC_E_MODEL"}
-LAYERS = ["GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3"]
+LAYERS = ["GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3",
+          "CX", "EP0A", "EP1A", "EP2A", "EP0N", "EP1N", "EP2N"]
 LAYER_ID = {n: i for i, n in enumerate(LAYERS)}

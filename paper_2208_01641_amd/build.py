@@ -16,7 +16,7 @@ OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblic.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HIP_SOURCES = ["conv_kernels.hip", "distill_kernels.hip"]
+HIP_SOURCES = ["conv_kernels.hip", "distill_kernels.hip", "context_kernels.hip"]
 CPP_SOURCES = ["entropy.cpp", "packing.cpp", "model.cpp", "pipeline.cpp", "server.cpp", "api.cpp", "distill.cpp"]
 
 HIPCC = [os.path.join(ROCM, "bin", "hipcc"), "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -79,8 +79,9 @@ class Codec:
     def max_stream_bytes(self, H: int, W: int) -> int:
         Hp, Wp = 64 * -(-H // 64), 64 * -(-W // 64)
         ny = (Hp // 16) * (Wp // 16) * self.M
-        nz = (Hp // 64) * (Wp // 64) * self.N if self.kind == 1 else 0
-        return 20 + 4 * (self.S + 1) + 2 * (ny + nz) + 160 * 65
+        nz = (Hp // 64) * (Wp // 64) * self.N if self.kind >= 1 else 0
+        ns = 2 * self.S if self.kind == 2 else self.S          # y streams
+        return 20 + 4 * (ns + 1) + 2 * (ny + nz) + 160 * (ns + 1)
 
     # ------------------------------------------------------------------
     def encode(self, x) -> list:
@@ -156,19 +157,25 @@ class Codec:
                                           ctypes.byref(b, 16)))
         return tuple(int(v) for v in b)
 
-    def run_layer(self, layer, n: int, H: int, W: int, inp, out, aux=None):
+    def run_layer(self, layer, n: int, H: int, W: int, inp, out, aux=None, in2=None, out2=None):
+        """One layer on device buffers.  in2 / out2: the last entropy-parameter
+        layer of the context model (y, and y_hat or the means)."""
         lid = _lib.LAYER_ID[layer] if isinstance(layer, str) else int(layer)
         # refuse buffers smaller than what the layer reads or writes
         need = self.layer_bytes(lid, n, H, W)
-        for name, t, nb in (("input", inp, need[0]), ("output", out, need[1]), ("aux", aux, need[2])):
+        pl = n * (64 * -(-H // 64) // 16) * (64 * -(-W // 64) // 16) * self.M * 4   # float latent tensor
+        ep2 = _lib.LAYERS[lid] in ("EP2A", "EP2N")
+        for name, t, nb in (("input", inp, need[0]), ("output", out, need[1]), ("aux", aux, need[2]),
+                            ("in2", in2, pl if ep2 else 0), ("out2", out2, pl if ep2 else 0)):
             if t is None or nb == 0:
                 continue
             have = t.numel() * t.element_size() if hasattr(t, "element_size") else t.nbytes
             if have < nb:
                 raise LicError(_lib.LIC_E_SMALLBUF, f"{_lib.LAYERS[lid]} {name} buffer holds {have} bytes, needs {nb}")
-        _sync(inp, out, aux)
-        self._check(lib.codec_run_layer(self._h, lid, n, H, W, _ptr(inp), 0 if out is None else _ptr(out),
-                                        0 if aux is None else _ptr(aux)))
+        _sync(inp, out, aux, in2, out2)
+        opt = lambda t: 0 if t is None else _ptr(t)    # noqa: E731
+        self._check(lib.codec_run_layer_ex(self._h, lid, n, H, W, _ptr(inp), opt(out), opt(aux), opt(in2),
+                                           opt(out2)))
 
     def latencies_ms(self) -> np.ndarray:
         buf = np.zeros(1 << 16, np.float64)

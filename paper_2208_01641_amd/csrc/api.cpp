@@ -25,6 +25,7 @@ int fail(Codec* c, int code, const std::string& msg)
 bool supported_shape(int kind, int N, int M)
 {
     const bool hyper_ok = (N == 128 && M == 192) || (N == 192 && M == 320);
+    if (kind == LIC_KIND_CONTEXT) return N == 128 && M == 192;
     return kind == LIC_KIND_HYPERPRIOR ? hyper_ok : (kind == LIC_KIND_FACTORIZED && hyper_ok);
 }
 
@@ -91,6 +92,10 @@ int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, cod
         return LIC_E_ARG;
     }
     if (cfg->hs_out != LIC_HS_EXP && cfg->hs_out != LIC_HS_RELU) { g_create_error = "bad hs_out"; return LIC_E_ARG; }
+    if (cfg->kind == LIC_KIND_CONTEXT && (cfg->precision == LIC_PREC_FP8 || cfg->gs_mode != 0)) {
+        g_create_error = "context model: FP32 or BF16 form with the full g_s";
+        return LIC_E_ARG;
+    }
     if (cfg->gs_mode < 0 || cfg->gs_mode > 2) { g_create_error = "gs_mode must be 0, 1 or 2"; return LIC_E_ARG; }
     if (cfg->norm != LIC_NORM_GDN && cfg->norm != LIC_NORM_1DN) { g_create_error = "bad norm"; return LIC_E_ARG; }
     if (cfg->rans_lanes != 0 && !lic::rans_lanes_valid(cfg->rans_lanes)) {
@@ -198,7 +203,10 @@ int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n, flo
     cs.n = n;
     cs.route.dims = lic::FrameDims(h, w);
     cs.route.is_device = is_device;
-    if (c->kind == LIC_KIND_HYPERPRIOR)
+    if (c->kind == LIC_KIND_CONTEXT)
+        cs.route.stages = {lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_CTX, lic::ST_CPU_DEC_Y2,
+                           lic::ST_GPU_GS};
+    else if (c->kind == LIC_KIND_HYPERPRIOR)
         cs.route.stages = {lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     else
         cs.route.stages = {lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
@@ -208,7 +216,7 @@ int codec_decode(codec_t* c, const uint8_t* bits, const size_t* lens, int n, flo
             const int f = t->first + b;
             t->zp[b] = zp[f];
             t->zlen[b] = zl[f];
-            for (int s = 0; s < cs.route.S; ++s) {
+            for (size_t s = 0; s < yp[f].size(); ++s) {
                 t->yp[b][s] = yp[f][s];
                 t->ylen[b][s] = yl[f][s];
             }
@@ -228,7 +236,10 @@ int codec_encode_decode(codec_t* c, const float* x, int n, int H, int W, int is_
     cs.route.S = c->S;
     cs.route.dims = lic::FrameDims(H, W);
     cs.route.is_device = is_device;
-    if (c->kind == LIC_KIND_HYPERPRIOR)
+    if (c->kind == LIC_KIND_CONTEXT)
+        cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC,     lic::ST_CPU_DEC_Z,  lic::ST_GPU_HS,
+                           lic::ST_CPU_DEC_Y, lic::ST_GPU_CTX, lic::ST_CPU_DEC_Y2, lic::ST_GPU_GS};
+    else if (c->kind == LIC_KIND_HYPERPRIOR)
         cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Z, lic::ST_GPU_HS, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
     else
         cs.route.stages = {lic::ST_GPU_ENC, lic::ST_CPU_ENC, lic::ST_CPU_DEC_Y, lic::ST_GPU_GS};
@@ -326,15 +337,23 @@ int codec_load_distilled(codec_t* c, const float* params, size_t n_params, float
 
 int codec_run_layer(codec_t* c, int layer, int n, int H, int W, const void* in, void* out, void* aux)
 {
+    return codec_run_layer_ex(c, layer, n, H, W, in, out, aux, nullptr, nullptr);
+}
+
+int codec_run_layer_ex(codec_t* c, int layer, int n, int H, int W, const void* in, void* out, void* aux,
+                       const void* in2, void* out2)
+{
     if (!c) return LIC_E_ARG;
     if (layer < 0 || layer >= LIC_NUM_LAYERS || !c->layers[layer].present) return fail(c, LIC_E_ARG, "no such layer");
     if (n < 1 || H < 1 || W < 1 || H > 65535 || W > 65535) return fail(c, LIC_E_ARG, "bad size");
     if (!in || (!out && layer != LIC_HA2 && layer != LIC_GA3)) return fail(c, LIC_E_ARG, "null buffer");
     if ((layer == LIC_GA3 || layer == LIC_HA2) && !aux) return fail(c, LIC_E_ARG, "quantising layers need aux");
+    if ((layer == LIC_EP2A || layer == LIC_EP2N) && !out2)
+        return fail(c, LIC_E_ARG, "the last entropy-parameter layer needs out2 (y_hat or the means)");
     lic::FrameDims d(H, W);
     if (hipSetDevice(c->cfg.hip_device) != hipSuccess) return fail(c, LIC_E_HIP, "hipSetDevice");
     std::string e;
-    int rc = c->launch_layer(layer, n, d, in, out, aux, c->layer_stream, &e);
+    int rc = c->launch_layer(layer, n, d, in, out, aux, c->layer_stream, &e, nullptr, in2, out2);
     if (rc != LIC_OK) return fail(c, rc, e);
     hipError_t he = hipStreamSynchronize(c->layer_stream);
     if (he != hipSuccess) return fail(c, LIC_E_HIP, hipGetErrorString(he));
@@ -491,6 +510,7 @@ int codec_submit_encode(codec_t* c, int stream_id, const float* x, int is_device
                         uint64_t* ticket)
 {
     if (!c || !x || !out || !ticket) return LIC_E_ARG;
+    if (c->kind == LIC_KIND_CONTEXT) return fail(c, LIC_E_ARG, "serving runs the factorized and hyperprior codecs");
     lic::Request* r = new (std::nothrow) lic::Request();
     if (!r) return fail(c, LIC_E_NOMEM, "out of memory");
     r->dir = 0;
@@ -506,6 +526,7 @@ int codec_submit_decode(codec_t* c, int stream_id, const uint8_t* bits, size_t l
                         int is_device, uint64_t* ticket)
 {
     if (!c || !bits || !x_hat || !ticket) return LIC_E_ARG;
+    if (c->kind == LIC_KIND_CONTEXT) return fail(c, LIC_E_ARG, "serving runs the factorized and hyperprior codecs");
     lic::Request* r = new (std::nothrow) lic::Request();
     if (!r) return fail(c, LIC_E_NOMEM, "out of memory");
     std::vector<const uint8_t*> yp;

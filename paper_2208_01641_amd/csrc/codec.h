@@ -100,13 +100,14 @@ struct Task {
     std::string err;
     double t_admit = 0.0, t_done = 0.0;
     size_t bits_len[kMaxBatch] = {};
-    // encoder: stream lengths (z = part 0 for the hyperprior, then y slices)
-    size_t part_len[kMaxBatch][kMaxSlices + 1] = {};
+    // encoder: stream lengths (z = part 0 for the hyperpriors, then the y
+    // streams: S slices, 2 S for the context model)
+    size_t part_len[kMaxBatch][2 * kMaxSlices + 1] = {};
     // decoder: payload spans of each parsed bitstream
     const uint8_t* zp[kMaxBatch] = {};
     size_t zlen[kMaxBatch] = {};
-    const uint8_t* yp[kMaxBatch][kMaxSlices] = {};
-    size_t ylen[kMaxBatch][kMaxSlices] = {};
+    const uint8_t* yp[kMaxBatch][2 * kMaxSlices] = {};
+    size_t ylen[kMaxBatch][2 * kMaxSlices] = {};
 
     void fail(int code, const std::string& msg)
     {
@@ -122,9 +123,11 @@ struct Task {
 // and mapped into the device address space, so the epilogues can store
 // symbols and indices straight into them (zero-copy) or a DMA copy can.
 struct Slot {
-    int8_t* h_sym_y = nullptr;   int8_t* d_sym_y = nullptr;    // [B][Hy][Wy][M]
-    int8_t* h_sym_z = nullptr;   int8_t* d_sym_z = nullptr;    // [B][Hz][Wz][N]
-    uint8_t* h_idx = nullptr;    uint8_t* d_idx = nullptr;     // [B][Hy][Wy][M]
+    int8_t* h_sym_y = nullptr;   int8_t* d_sym_y = nullptr;    // [B][Hy][Wy][M] (context model:
+    int8_t* h_sym_z = nullptr;   int8_t* d_sym_z = nullptr;    // [B][Hz][Wz][N]  checkerboard-major
+    uint8_t* h_idx = nullptr;    uint8_t* d_idx = nullptr;     // [B][Hy][Wy][M]  y symbols and indices)
+    float* d_zc = nullptr;       // context model: [psi; ctx], [B][Hy][Wy][4M]
+    float* d_mu = nullptr;       // context model (decoder): the means, checkerboard-major
     int8_t* dm_sym_y = nullptr;  uint8_t* dm_idx = nullptr;    // device views of the pinned buffers
     uint8_t* h_scratch = nullptr; size_t scratch_per_frame = 0; // per-stream rANS output regions
     uint8_t* h_bits = nullptr;    size_t bits_per_frame = 0;    // assembled bitstreams
@@ -139,9 +142,15 @@ struct StageScratch {
     float* y = nullptr;   // M x Hy x Wy
     float* h1 = nullptr;  // N x Hy x Wy
     float* h2 = nullptr;  // N x Hy/2 x Wy/2 (and h_s middle: N x Hy/2 x Wy/2)
+    float* e1 = nullptr;  // context model: entropy-parameter hidden layers (E1, E2 x Hy x Wy)
+    float* e2 = nullptr;
+    float* yh = nullptr;  // context model: y_hat M x Hy x Wy (float32, or bf16 for g_s)
 };
 
-enum StageKind { ST_GPU_ENC, ST_CPU_ENC, ST_CPU_DEC_Z, ST_GPU_HS, ST_CPU_DEC_Y, ST_GPU_GS };
+// ST_GPU_CTX and ST_CPU_DEC_Y2: the context model's second pass (the context
+// of the decoded anchors and the other positions' parameters, then their
+// symbols); ST_CPU_DEC_Y then decodes the anchors only
+enum StageKind { ST_GPU_ENC, ST_CPU_ENC, ST_CPU_DEC_Z, ST_GPU_HS, ST_CPU_DEC_Y, ST_GPU_GS, ST_GPU_CTX, ST_CPU_DEC_Y2 };
 
 // What every task of a call (or of a serving bucket) shares.
 struct Route {
@@ -288,7 +297,8 @@ struct Codec {
 
     // runtime
     hipStream_t layer_stream = nullptr;      // codec_run_layer
-    GpuStage gpu[3];                         // encoder GPU, decoder GPU1 (h_s), decoder GPU2 (g_s)
+    GpuStage gpu[3];                         // encoder GPU, decoder GPU1 (h_s and the context
+                                             // model's second pass), decoder GPU2 (g_s)
     std::vector<Slot> slots;
     BlockingQueue<int> free_slots;
     BlockingQueue<Job> jobs;
@@ -339,8 +349,11 @@ struct Codec {
     // Bytes of a layer's input, output and aux tensors for n frames of d
     // (codec_run_layer's buffers; 0 where the layer takes none).
     void layer_bytes(int layer, int n, const FrameDims& d, size_t* in, size_t* out, size_t* aux) const;
+    // in2 / out2: the last entropy-parameter layer of the context model
+    // (ConvArgs::ysrc, ConvArgs::yq)
     int launch_layer(int layer, int n, const FrameDims& d, const void* in, void* out, void* aux,
-                     hipStream_t s, std::string* errp, KernelKey* chosen = nullptr);
+                     hipStream_t s, std::string* errp, KernelKey* chosen = nullptr, const void* in2 = nullptr,
+                     void* out2 = nullptr);
     // e4m3 form: per-row scales of a layer's epilogue (weight scale x input scale)
     int upload_rscale(LayerGPU& L);
     // e4m3 form: activation scales from calibration frames (device, n x 3 x H x W)
@@ -357,6 +370,7 @@ struct Codec {
     void finish_task(Task* t);
     int gpu_encode(Task* t, GpuStage& g);
     int gpu_hs(Task* t, GpuStage& g);
+    int gpu_ctx(Task* t, GpuStage& g);
     int gpu_gs(Task* t, GpuStage& g);
     int cpu_job(Task* t, int frame, int part);
     int cpu_parts(const Task* t, StageKind k) const;   // jobs per frame

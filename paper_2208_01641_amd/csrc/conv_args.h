@@ -28,7 +28,16 @@ enum Epilogue : int {
     EP_RGB = 6,      // transposed conv to 3 channels, all S x S phases as 3 S^2
                      // GEMM rows: out = clamp(v, 0, 1) cropped NCHW, aux = v NCHW
     EP_MASK = 7,     // out = v where aux (forward activation) > 0, else 0
+    EP_MSCALE = 8,   // context model: GEMM rows in pairs (mean, pre-activation scale)
+                     // of one latent channel; out = scale-table index uint8, aux =
+                     // clamp(rne(y - mean), -64, 64) int8 (with ysrc), both in the
+                     // checkerboard-major layout; yq = sym + mean on the full grid
+                     // (with ysrc) or the mean, checkerboard-major (without)
 };
+
+// Checkerboard-major layout of a latent tensor [n][Hy][Wy][C] split by the
+// two-pass order: [n][part][Hy][Wy/2][C], part 0 the anchors ((r + c) even),
+// part 1 the rest; entry j of row r is column 2 j + ((r + part) & 1).
 
 // Operand precision of a layer's GEMM.
 enum DType : int {
@@ -85,6 +94,11 @@ struct ConvArgs {
     unsigned long long* sat; // e4m3 stores: count of values clamped to +-448 (null: not counted)
     int out_bf16;            // DT_FP8 kernels: store bf16 instead of e4m3 (the e4m3 form's
                              // last GDN layer feeds an output layer on bf16 operands)
+    int co_ld, co_off;       // activation stores: channel stride of the output tensor
+                             // (0: Co) and first channel written (concatenated tensors)
+    const float* ysrc;       // EP_MSCALE: y, NHWC full grid (encoder), or null (decoder)
+    float* yq;               // EP_MSCALE: y_hat (encoder) or mean (decoder), see EP_MSCALE
+    int cb_part;             // EP_MSCALE: the checkerboard set the phases cover (0, 1)
 };
 
 }  // namespace lic

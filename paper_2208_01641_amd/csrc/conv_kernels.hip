@@ -1042,11 +1042,12 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // ------------------------------------------------------------ epilogue
     long obase[NT];
     int oy[NT], ox[NT];
+    const long ldo = a.co_ld ? a.co_ld : a.Co;
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         oy[nt] = gy[nt] * a.s_out + ph->oy;
         ox[nt] = gx[nt] * a.s_out + ph->ox;
-        obase[nt] = (((long)img[nt] * a.Hout + oy[nt]) * a.Wout + ox[nt]) * a.Co;
+        obase[nt] = (((long)img[nt] * a.Hout + oy[nt]) * a.Wout + ox[nt]) * ldo + a.co_off;
     }
 
     // Byte outputs (symbols, scale indices) often go straight to mapped host
@@ -1054,6 +1055,21 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // channel bytes as whole 16-byte pieces (one 64-byte line for MT = 4)
     // rather than 4-byte pieces spread over the lanes.
     constexpr bool kBytes = EP == EP_QUANT || EP == EP_INDEX;
+    // scale-table index of a pre-activation scale y: #{k < 63 : thr[k] < s}
+    // with s = y (thr holds ln t_k: exp(y) > t_k <=> y > ln t_k) or s =
+    // max(y, 0, t_0) (thr holds t_k).  The table is log-spaced, so (s -
+    // thr[0]) / step (ReLU: log2(s / thr[0]) / step) is within a step or two
+    // of the count; from there the count is settled by comparisons with the
+    // table itself (ts, staged per wave in LDS), so the result is exactly the
+    // count whatever the first guess.
+    auto scale_count = [&](float y, const float* ts, float t0, float inv) __attribute__((always_inline)) {
+        const float s = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), t0);
+        const float u = a.hs_exp ? (s - t0) * inv : __log2f(s / t0) * inv;
+        int e = (int)ceilf(fminf(fmaxf(u, 0.0f), 63.0f));     // NaN: 0
+        while (e < 63 && ts[e] < s) ++e;
+        while (e > 0 && !(ts[e - 1] < s)) --e;
+        return e;
+    };
     __shared__ __attribute__((aligned(16))) uint32_t obytes[kBytes ? PIXW : 1][kBytes ? NT * 16 : 1][kBytes ? MT * 4 : 1];
     auto store_bytes = [&](const uint32_t (&pk)[MT][NT], uint8_t* dst) __attribute__((always_inline)) {
         uint32_t (&w)[kBytes ? NT * 16 : 1][kBytes ? MT * 4 : 1] = obytes[wave / KSPLIT];
@@ -1245,12 +1261,6 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         uint8_t* idxo = static_cast<uint8_t*>(a.out);
         float* vout = static_cast<float*>(a.aux);
         const float* __restrict__ thr = a.thr;
-        // idx = #{k < 63 : thr[k] < s} with s = v (thr holds ln t_k: exp(v) >
-        // t_k <=> v > ln t_k) or s = max(v, 0, t_0) (thr holds t_k).  The
-        // table is log-spaced, so (s - thr[0]) / step (ReLU: log2(s / thr[0])
-        // / step) is within a step or two of the count; from there the count
-        // is settled by comparisons with the table itself (staged per wave in
-        // LDS), so the result is exactly the count whatever the first guess.
         __shared__ float thr_s[PIXW][64];
         float* const ts = thr_s[wave / KSPLIT];
         ts[lane] = lane < 63 ? thr[lane] : __builtin_inff();
@@ -1265,15 +1275,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const float y = acc[mt][nt][i];
-                    const float s = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), t0);
-                    const float u = a.hs_exp ? (s - t0) * inv : __log2f(s / t0) * inv;
-                    int e = (int)ceilf(fminf(fmaxf(u, 0.0f), 63.0f));     // NaN: 0
-                    while (e < 63 && ts[e] < s) ++e;
-                    while (e > 0 && !(ts[e - 1] < s)) --e;
-                    cnt[mt][nt][i] = e;
-                }
+                for (int i = 0; i < 4; ++i) cnt[mt][nt][i] = scale_count(acc[mt][nt][i], ts, t0, inv);
         uint32_t pk[MT][NT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt)
@@ -1287,6 +1289,47 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
                 if (vout && pv[nt] && c < a.Co) *reinterpret_cast<f4*>(vout + obase[nt] + c) = acc[mt][nt];
             }
         store_bytes(pk, idxo);
+    } else if constexpr (EP == EP_MSCALE) {
+        // rows 2c, 2c + 1 of the tile are the mean and the pre-activation
+        // scale of latent channel c: the f4 of lane group kg holds channels
+        // c0, c0 + 1 with c0 = (co0 + 16 mt + 4 kg) / 2
+        const int M = a.Co / 2, Wh = a.Wout / 2;
+        uint8_t* idxo = static_cast<uint8_t*>(a.out);
+        int8_t* symo = static_cast<int8_t*>(a.aux);
+        const float* __restrict__ thr = a.thr;
+        __shared__ float thr_s[PIXW][64];
+        float* const ts = thr_s[wave / KSPLIT];
+        ts[lane] = lane < 63 ? thr[lane] : __builtin_inff();
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        const float t0 = thr[0];
+        const float inv = a.hs_exp ? 62.0f / (thr[62] - t0) : 62.0f / __log2f(thr[62] / t0);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            // checkerboard-major element of this pixel: entry gx of row oy
+            const long cpix = (((long)img[nt] * 2 + a.cb_part) * a.Hout + oy[nt]) * Wh + gx[nt];
+            const long fpix = ((long)img[nt] * a.Hout + oy[nt]) * a.Wout + ox[nt];
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const int c0 = (co0 + mt * 16 + kg * 4) / 2;
+                if (!pv[nt] || c0 >= M) continue;
+                const f4 v = acc[mt][nt];
+                const int e0 = scale_count(v[1], ts, t0, inv), e1 = scale_count(v[3], ts, t0, inv);
+                *reinterpret_cast<uint16_t*>(idxo + cpix * M + c0) = (uint16_t)(e0 | (e1 << 8));
+                if (a.ysrc) {
+                    const float2 y = *reinterpret_cast<const float2*>(a.ysrc + fpix * M + c0);
+                    const float q0 = fminf(fmaxf(rintf(y.x - v[0]), -64.0f), 64.0f);
+                    const float q1 = fminf(fmaxf(rintf(y.y - v[2]), -64.0f), 64.0f);
+                    if (symo)
+                        *reinterpret_cast<uint16_t*>(symo + cpix * M + c0) =
+                            (uint16_t)(((uint32_t)((int)q0) & 0xffu) | (((uint32_t)((int)q1) & 0xffu) << 8));
+                    *reinterpret_cast<float2*>(a.yq + fpix * M + c0) = make_float2(q0 + v[0], q1 + v[2]);
+                } else {
+                    *reinterpret_cast<float2*>(a.yq + cpix * M + c0) = make_float2(v[0], v[2]);
+                }
+            }
+        }
     } else if constexpr (EP == EP_RGB) {
         // rows r = 3 (S py + px) + c are the S x S sub-pixel phases of the 3
         // output channels of a stride-S transposed convolution (S = s_out)
@@ -1381,6 +1424,17 @@ static const KernelEntry kEntries[] = {
     LIC_K2(LIC_HS0, 128, LD_I8, EP_RELU), LIC_K2(LIC_HS0, 192, LD_I8, EP_RELU),
     LIC_K2(LIC_HS1, 128, LD_F32, EP_RELU), LIC_K2(LIC_HS1, 192, LD_F32, EP_RELU),
     LIC_K2(LIC_HS2, 128, LD_F32, EP_INDEX), LIC_K2(LIC_HS2, 192, LD_F32, EP_INDEX),
+    // context model (N = 128, M = 192): h_a on y, h_s to psi, the context
+    // convolution, the entropy-parameter layers of both passes, g_s from y_hat
+    LIC_K2(LIC_HA0, 192, LD_F32, EP_RELU), LIC_K2(LIC_HS2, 128, LD_F32, EP_NONE),
+    LIC_K2(LIC_CX, 192, LD_F32, EP_NONE),
+    LIC_K2(LIC_EP0A, 768, LD_F32, EP_RELU), LIC_K2(LIC_EP1A, 640, LD_F32, EP_RELU),
+    LIC_K2(LIC_EP2A, 512, LD_F32, EP_MSCALE),
+    LIC_K2(LIC_EP0N, 768, LD_F32, EP_RELU), LIC_K2(LIC_EP1N, 640, LD_F32, EP_RELU),
+    LIC_K2(LIC_EP2N, 512, LD_F32, EP_MSCALE),
+    LIC_KG(LIC_GS0, 192, 8, 2, LD_F32, EP_IGDN), LIC_KX(LIC_GS0, 192, 8, 2, LD_F32, EP_IGDN),
+    LIC_KX(LIC_GS0, 192, 8, 1, LD_F32, EP_IGDN), LIC_KGB(LIC_GS0, 192, 8, 2, LD_F32, EP_IGDN),
+    LIC_KB(LIC_GS0, 192, 8, 1, 4, LD_F32, EP_IGDN),
     // g_s
     LIC_KG(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KG(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
     LIC_KG(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KG(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),

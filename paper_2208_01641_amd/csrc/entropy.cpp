@@ -456,8 +456,8 @@ void write_header(uint8_t* out, const StreamHeader& h, uint32_t len_z, const uin
     put16(out + 14, h.M);
     put32(out + 16, h.model_id);
     uint8_t* p = out + kHeaderBytes;
-    if (h.kind == 1) { put32(p, len_z); p += 4; }
-    for (int s = 0; s < h.S; ++s, p += 4) put32(p, len_y[s]);
+    if (h.kind >= 1) { put32(p, len_z); p += 4; }
+    for (int s = 0; s < y_streams(h.kind, h.S); ++s, p += 4) put32(p, len_y[s]);
 }
 
 bool parse_stream(const uint8_t* bits, size_t len, StreamHeader* h, const uint8_t** z, size_t* len_z,
@@ -476,21 +476,22 @@ bool parse_stream(const uint8_t* bits, size_t len, StreamHeader* h, const uint8_
     h->N = (int)get16(bits + 12);
     h->M = (int)get16(bits + 14);
     h->model_id = get32(bits + 16);
-    if ((h->kind != 0 && h->kind != 1) || h->S < 1 || h->H < 1 || h->W < 1) { *err = "bad header"; return false; }
+    if (h->kind < 0 || h->kind > 2 || h->S < 1 || h->H < 1 || h->W < 1) { *err = "bad header"; return false; }
     const size_t hs = header_size(h->kind, h->S);
     if (len < hs) { *err = "truncated header"; return false; }
     const uint8_t* p = bits + kHeaderBytes;
     size_t pos = hs;
     *z = nullptr;
     *len_z = 0;
-    if (h->kind == 1) { *len_z = get32(p); p += 4; }
-    len_y->resize(h->S);
-    y->resize(h->S);
+    if (h->kind >= 1) { *len_z = get32(p); p += 4; }
+    const int ny = y_streams(h->kind, h->S);
+    len_y->resize(ny);
+    y->resize(ny);
     size_t total = *len_z;
-    for (int s = 0; s < h->S; ++s, p += 4) { (*len_y)[s] = get32(p); total += (*len_y)[s]; }
+    for (int s = 0; s < ny; ++s, p += 4) { (*len_y)[s] = get32(p); total += (*len_y)[s]; }
     if (total != len - hs) { *err = "payload length mismatch"; return false; }
-    if (h->kind == 1) { *z = bits + pos; pos += *len_z; }
-    for (int s = 0; s < h->S; ++s) { (*y)[s] = bits + pos; pos += (*len_y)[s]; }
+    if (h->kind >= 1) { *z = bits + pos; pos += *len_z; }
+    for (int s = 0; s < ny; ++s) { (*y)[s] = bits + pos; pos += (*len_y)[s]; }
     return true;
 }
 

@@ -86,7 +86,11 @@ constexpr size_t kHeaderBytes = 20;
 // room beyond 2 bytes per symbol that one rANS stream may need (the final
 // states: 4 bytes byte-wise, 4 K interleaved)
 constexpr size_t kStreamSlack = 160;
-inline size_t header_size(int kind, int S) { return kHeaderBytes + 4u * (S + (kind == 1 ? 1 : 0)); }
+// y streams of a bitstream: S row slices, twice for the context model (the
+// anchors' S slices, then the other positions' S slices)
+inline int y_streams(int kind, int S) { return kind == 2 ? 2 * S : S; }
+inline size_t header_size(int kind, int S) { return kHeaderBytes + 4u * (y_streams(kind, S) + (kind >= 1 ? 1 : 0)); }
+// len_y: y_streams(h.kind, h.S) lengths
 void write_header(uint8_t* out, const StreamHeader& h, uint32_t len_z, const uint32_t* len_y);
 // Validates and returns the payload spans; false on any inconsistency.
 bool parse_stream(const uint8_t* bits, size_t len, StreamHeader* h,

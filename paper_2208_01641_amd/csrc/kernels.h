@@ -23,6 +23,16 @@ struct KernelKey {
 bool kernel_available(const KernelKey& k);
 hipError_t launch_conv(const KernelKey& k, const ConvArgs& args, int nblocks, hipStream_t stream);
 
+// Context model, element-wise steps of the two checkerboard passes (layout
+// in conv_args.h): value into channels [off, off + C) of a [n][Hy][Wy][ld]
+// float tensor at the positions of set `part`; y_hat = sym + mean of set
+// `part` (checkerboard-major inputs) onto the full [n][Hy][Wy][C] grid as
+// float32 (out32) and / or bf16 (out16), either may be null.
+hipError_t launch_cb_fill(float* buf, int n, int Hy, int Wy, int ld, int off, int C, int part, float value,
+                          hipStream_t s);
+hipError_t launch_cb_dequant(const int8_t* sym, const float* mean, float* out32, void* out16, int n, int Hy, int Wy,
+                             int C, int part, hipStream_t s);
+
 // Kernel tags beyond the codec's layer ids: the distilled synthesis network
 // (forward layers, and the input gradients of its second and third layer).
 enum { TAG_DT1 = 32, TAG_DT2 = 33, TAG_DT3 = 34, TAG_DB2 = 35, TAG_DB3 = 36 };

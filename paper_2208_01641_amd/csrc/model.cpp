@@ -179,7 +179,7 @@ bool build_tables(const ParamMap& P, int kind, int N, int M, std::vector<float>*
         quantize_pmf(pmf.data(), fact_freq->data() + (size_t)c * kNumSym);
     }
     gauss_freq->clear();
-    if (kind == 1) {
+    if (kind >= 1) {
         double t[kScales];
         scale_table(t);
         gauss_freq->assign((size_t)kScales * kNumSym, 0);
@@ -213,7 +213,7 @@ int Codec::load(const void* blob, size_t len)
     std::vector<uint32_t> ff, gf;
     if (!build_tables(P, kind, N, M, &medians, &ff, &gf, &err)) return LIC_E_MODEL;
     fact.init(kind == 0 ? M : N, ff.data(), kind == 0);
-    if (kind == 1) {
+    if (kind >= 1) {
         gauss.init(kScales, gf.data(), true);
         double t[kScales];
         scale_table(t);
@@ -248,6 +248,7 @@ struct Spec {
     int ld, ep;
     bool deconv;
     int k;
+    int cb = -1;       // context model: the checkerboard set the layer is evaluated on
 };
 
 }  // namespace
@@ -365,13 +366,28 @@ int Codec::build_layers(const ParamMap& P)
         {LIC_GS0, "gs0", LD_I8, EP_IGDN, true, 5},  {LIC_GS1, "gs1", LD_F32, EP_IGDN, true, 5},
         {LIC_GS2, "gs2", LD_F32, EP_IGDN, true, 5}, {LIC_GS3, "gs3", LD_F32, EP_RGB, true, 5},
     };
-    if (kind == 1) {
+    if (kind >= 1) {
+        // the context model's h_a sees y (the means need its signs), its h_s
+        // ends in psi (2M channels, no activation) and g_s starts from the
+        // float y_hat = sym + mean
         std::vector<Spec> hyper = {
-            {LIC_HA0, "ha0", LD_F32_ABS, EP_RELU, false, 3}, {LIC_HA1, "ha1", LD_F32, EP_RELU, false, 5},
+            {LIC_HA0, "ha0", kind == 1 ? LD_F32_ABS : LD_F32, EP_RELU, false, 3},
+            {LIC_HA1, "ha1", LD_F32, EP_RELU, false, 5},
             {LIC_HA2, "ha2", LD_F32, EP_QUANT, false, 5},    {LIC_HS0, "hs0", LD_I8, EP_RELU, true, 5},
-            {LIC_HS1, "hs1", LD_F32, EP_RELU, true, 5},      {LIC_HS2, "hs2", LD_F32, EP_INDEX, false, 3},
+            {LIC_HS1, "hs1", LD_F32, EP_RELU, true, 5},
+            {LIC_HS2, "hs2", LD_F32, kind == 1 ? EP_INDEX : EP_NONE, false, 3},
         };
         specs.insert(specs.end(), hyper.begin(), hyper.end());
+    }
+    if (kind == 2) {
+        specs[4].ld = LD_F32;                            // gs0
+        std::vector<Spec> ctx = {
+            {LIC_CX, "cx", LD_F32, EP_NONE, false, 5, 1},
+            {LIC_EP0A, "ep0", LD_F32, EP_RELU, false, 1, 0},   {LIC_EP1A, "ep1", LD_F32, EP_RELU, false, 1, 0},
+            {LIC_EP2A, "ep2", LD_F32, EP_MSCALE, false, 1, 0}, {LIC_EP0N, "ep0", LD_F32, EP_RELU, false, 1, 1},
+            {LIC_EP1N, "ep1", LD_F32, EP_RELU, false, 1, 1},   {LIC_EP2N, "ep2", LD_F32, EP_MSCALE, false, 1, 1},
+        };
+        specs.insert(specs.end(), ctx.begin(), ctx.end());
     }
 
     for (const Spec& sp : specs) {
@@ -399,7 +415,7 @@ int Codec::build_layers(const ParamMap& P)
         L.rows = sp.ep == EP_RGB;
         // bf16 operands for the analysis / synthesis transforms in the BF16
         // form; h_a and h_s always run in FP32 (fixed-order scale index)
-        const bool is_gags = sp.id <= LIC_GA3 || sp.id >= LIC_GS0;
+        const bool is_gags = sp.id <= LIC_GA3 || (sp.id >= LIC_GS0 && sp.id <= LIC_GS3);
         L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
         // the e4m3 form's image layer: bf16 operands (a K of 75 is one
         // chunk; pixel values keep 8 bits), e4m3 activations out
@@ -419,7 +435,8 @@ int Codec::build_layers(const ParamMap& P)
         if (L.rows && co != 3) { err = "gs3 must produce 3 channels"; return LIC_E_MODEL; }
         // packed GEMM operands as index maps into the PyTorch-layout weights
         PackMap pm;
-        if (sp.ld == LD_RGB) pm = pack_map(PK_IMG, 3, co, k, 2, k / 2, false, krgb);
+        if (sp.cb >= 0) pm = pack_map_checkerboard(ci, co, k, sp.cb, sp.ep == EP_MSCALE);
+        else if (sp.ld == LD_RGB) pm = pack_map(PK_IMG, 3, co, k, 2, k / 2, false, krgb);
         else if (!sp.deconv) pm = pack_map(PK_CONV, ci, co, k, 1, k / 2, false);
         else if (!L.rows) pm = pack_map(PK_DECONV, ci, co, k, 2, k / 2, true);
         else pm = pack_map(PK_ROWS, ci, co, k, 2, k / 2, true);
@@ -527,6 +544,16 @@ int Codec::build_layers(const ParamMap& P)
         if (sp.id == LIC_HS0) L.d_mu_in = d_medians;
         if (sp.id == LIC_GS0) L.d_mu_in = kind == 0 ? d_medians : d_zero;
     }
+    if (kind == 2) {
+        // kernels are instantiated for these widths (the entropy-parameter
+        // layers' K is a template parameter)
+        if (N != 128 || M != 192 || layers[LIC_EP1A].cin != 640 || layers[LIC_EP2A].cin != 512 ||
+            layers[LIC_EP0A].cin != 4 * M || layers[LIC_EP2A].co != 2 * M || layers[LIC_HS2].co != 2 * M ||
+            layers[LIC_CX].co != 2 * M || layers[LIC_CX].cin != M) {
+            err = "context model: kernels exist for N = 128, M = 192 (entropy-parameter widths 768, 640, 512, 384)";
+            return LIC_E_MODEL;
+        }
+    }
     return LIC_OK;
 }
 
@@ -548,6 +575,8 @@ Geo Codec::geo(int id, const FrameDims& d) const
     case LIC_GS1: return {Hp / 8, Wp / 8, Hp / 8, Wp / 8, 1, Hp / 4, Wp / 4, 2};
     case LIC_GS2: return {Hp / 4, Wp / 4, Hp / 4, Wp / 4, 1, Hp / 2, Wp / 2, 2};
     case LIC_GS3: return {Hp / 2, Wp / 2, Hp / 2, Wp / 2, 1, Hp, Wp, 2};
+    case LIC_CX: case LIC_EP0A: case LIC_EP1A: case LIC_EP2A: case LIC_EP0N: case LIC_EP1N: case LIC_EP2N:
+        return {Hy, Wy, Hy / 2, Wy / 2, 2, Hy, Wy, 2};        // two stride-2 sub-grids per set
     }
     return {0, 0, 0, 0, 0, 0, 0, 0};
 }
@@ -567,9 +596,22 @@ void Codec::layer_bytes(int id, int n, const FrameDims& d, size_t* in, size_t* o
     const size_t img = nn * 3 * d.H * d.W;
     const size_t px_in = nn * g.Hin * g.Win, px_out = nn * g.Hout * g.Wout;
     *aux = 0;
+    if (id >= LIC_CX) {
+        // context model (float32 tensors on the full latent grid): cx reads
+        // y_hat, ep0 the concatenation [psi; ctx] (4M channels), ep1 / ep2 the
+        // hidden layers; ep2 writes indices (and symbols) checkerboard-major
+        const size_t pl = nn * d.Hy * d.Wy;
+        const LayerGPU& L = layers[id];
+        *in = pl * L.cin * 4;
+        if (id == LIC_CX) *out = pl * 4 * M * 4;
+        else if (L.ep == EP_MSCALE) { *out = pl * M; *aux = pl * M; }
+        else *out = pl * L.co * 4;
+        return;
+    }
     // input: the image, int8 symbols, y / z / hyper activations (FP32), or
     // the previous layer's stored activations
     if (id == LIC_GA0) *in = img * 4;
+    else if (id == LIC_GS0 && kind == 2) *in = px_in * layers[id].cin * (layers[id].dt == DT_F32 ? 4 : 2);
     else if (id == LIC_HS0 || id == LIC_GS0) *in = px_in * layers[id].cin;
     else if (id >= LIC_HA0 && id <= LIC_HS2) *in = px_in * layers[id].cin * 4;
     else *in = px_in * layers[id].cin * act_bytes(layers[id - 1]);
@@ -579,6 +621,10 @@ void Codec::layer_bytes(int id, int n, const FrameDims& d, size_t* in, size_t* o
         *aux = px_out * layers[id].co;
         break;
     case LIC_HS2:                                     // uint8 indices, float values
+        if (kind == 2) {                              // psi into [psi; ctx]
+            *out = px_out * 4 * M * 4;
+            break;
+        }
         *out = px_out * layers[id].co;
         *aux = px_out * layers[id].co * 4;
         break;
@@ -595,7 +641,7 @@ void Codec::layer_bytes(int id, int n, const FrameDims& d, size_t* in, size_t* o
 }
 
 int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void* out, void* aux, hipStream_t s,
-                        std::string* errp, KernelKey* chosen)
+                        std::string* errp, KernelKey* chosen, const void* in2, void* out2)
 {
     if (id < 0 || id >= LIC_NUM_LAYERS || !layers[id].present) { *errp = "layer not present in this model"; return LIC_E_ARG; }
     const LayerGPU& L = layers[id];
@@ -637,6 +683,19 @@ int Codec::launch_layer(int id, int n, const FrameDims& d, const void* in, void*
     a.out_e4m3 = L.out_e4m3 ? 1 : 0;
     a.out_bf16 = L.out_bf16 ? 1 : 0;
 
+    // context model: psi and the context fill the two halves of [psi; ctx];
+    // the last entropy-parameter layer takes y (encoder) and writes y_hat or
+    // the means
+    if (kind == 2 && (id == LIC_HS2 || id == LIC_CX)) {
+        a.co_ld = 4 * M;
+        a.co_off = id == LIC_CX ? 2 * M : 0;
+    }
+    if (L.ep == EP_MSCALE) {
+        if (!out2 && !chosen) { *errp = "the last entropy-parameter layer needs its y_hat / mean output"; return LIC_E_ARG; }
+        a.cb_part = id == LIC_EP2A ? 0 : 1;
+        a.ysrc = static_cast<const float*>(in2);
+        a.yq = static_cast<float*>(out2);
+    }
     const ConvShape shape{id, L.ld, L.ep, L.dt, L.cin, L.cop, L.nphase, L.halo1 && g.s_in == 1 ? 1 : 0};
     return launch_conv_policy(shape, a, (long)g.Hg * g.Wg, s, errp, chosen);
 }

@@ -123,4 +123,43 @@ PackMap pack_map(PackKind kind, int ci, int co, int k, int s, int p, bool w_deco
     return m;
 }
 
+PackMap pack_map_checkerboard(int ci, int co, int k, int part, bool pair_rows)
+{
+    PackMap m;
+    m.cin = ci;
+    m.cop = 16 * ((co + 15) / 16);
+    const int p = k / 2;
+    auto row_of = [&](int o) { return pair_rows ? (o < co / 2 ? 2 * o : 2 * (o - co / 2) + 1) : o; };
+    const int phases[2][2][2] = {{{0, 0}, {1, 1}}, {{0, 1}, {1, 0}}};
+    for (int f = 0; f < 2; ++f) {
+        PhaseDesc d{};
+        d.oy = phases[part][f][0];
+        d.ox = phases[part][f][1];
+        std::vector<int> us, vs;
+        for (int u = 0; u < k; ++u)
+            for (int v = 0; v < k; ++v)
+                if (k == 1 || (u + v - 2 * p) % 2 != 0) {
+                    us.push_back(u);
+                    vs.push_back(v);
+                }
+        d.ntaps = (int)us.size();
+        for (int t = 0; t < d.ntaps; ++t) {
+            d.dy[t] = (int8_t)(d.oy + us[t] - p);
+            d.dx[t] = (int8_t)(d.ox + vs[t] - p);
+        }
+        m.ph.push_back(d);
+        m.off.push_back(m.idx.size());
+        const size_t base = m.idx.size();
+        m.idx.resize(base + (size_t)d.ntaps * m.cop * ci, -1);
+        for (int t = 0; t < d.ntaps; ++t)
+            for (int o = 0; o < co; ++o)
+                for (int c = 0; c < ci; ++c)
+                    m.idx[base + ((size_t)t * m.cop + row_of(o)) * ci + c] =
+                        (int32_t)((((long)o * ci + c) * k + us[t]) * k + vs[t]);
+    }
+    m.bias_idx.assign(m.cop, -1);
+    for (int o = 0; o < co; ++o) m.bias_idx[row_of(o)] = o;
+    return m;
+}
+
 }  // namespace lic

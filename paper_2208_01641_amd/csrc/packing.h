@@ -37,4 +37,15 @@ struct PackMap {
 // convolution) instead of [co][ci][k][k]; kimg: packed K for PK_IMG.
 PackMap pack_map(PackKind kind, int ci, int co, int k, int s, int p, bool w_deconv, int kimg = 0);
 
+// A stride-1 convolution ([co][ci][k][k] weights) evaluated only at one set
+// of the checkerboard order of a latent grid: part 0 the anchors ((r + c)
+// even), part 1 the rest.  Each set is two stride-2 sub-grids, so the GEMM
+// runs over the Hy/2 x Wy/2 grid with two phases: output (2 a + oy, 2 b + ox)
+// with (oy, ox) = (0, 0), (1, 1) for the anchors and (0, 1), (1, 0) for the
+// rest, input 2 (a, b) + (oy + u - k/2, ox + v - k/2).  k = 1: the one tap;
+// k > 1: only the taps (u, v) with u + v - 2 (k/2) odd (the context mask, whose
+// taps from a non-anchor all fall on anchors).  pair_rows: packed rows 2 c and
+// 2 c + 1 hold output channels c and co/2 + c (mean and scale of latent c).
+PackMap pack_map_checkerboard(int ci, int co, int k, int part, bool pair_rows);
+
 }  // namespace lic

@@ -60,14 +60,31 @@ double now_s()
         }                                                                          \
     } while (0)
 
+// the same for the last entropy-parameter layer (second input and output)
+#define LAUNCH2(layer, in, out, aux, in2, out2, stream)                            \
+    do {                                                                           \
+        const bool timed_ = !G.capturing && ((timed_mask.load() >> (layer)) & 1u);  \
+        if (timed_) (void)hipEventRecord(G.lev[G.cur][layer][0], stream);          \
+        std::string e_;                                                            \
+        int r_ = launch_layer(layer, t->nb, d, in, out, aux, stream, &e_, nullptr, in2, out2); \
+        if (r_ != LIC_OK) {                                                        \
+            t->fail(r_, e_);                                                       \
+            return r_;                                                             \
+        }                                                                          \
+        if (timed_) {                                                              \
+            (void)hipEventRecord(G.lev[G.cur][layer][1], stream);                  \
+            G.lrec[G.cur][layer] = true;                                           \
+        }                                                                          \
+    } while (0)
+
 static int stage_gpu_index(StageKind k)
 {
-    return k == ST_GPU_ENC ? 0 : k == ST_GPU_HS ? 1 : k == ST_GPU_GS ? 2 : -1;
+    return k == ST_GPU_ENC ? 0 : (k == ST_GPU_HS || k == ST_GPU_CTX) ? 1 : k == ST_GPU_GS ? 2 : -1;
 }
 
 // worst case rANS output: 2 bytes per symbol (f = 1) + 4 state bytes per
 // stream; regions of the per-frame scratch: z first, then each y slice
-static size_t scratch_bytes(size_t ny, size_t nz) { return 2 * (ny + nz) + kStreamSlack * (kMaxSlices + 1); }
+static size_t scratch_bytes(size_t ny, size_t nz) { return 2 * (ny + nz) + kStreamSlack * (2 * kMaxSlices + 1); }
 
 // ----------------------------------------------------------------- start
 int Codec::start()
@@ -75,7 +92,7 @@ int Codec::start()
     const FrameDims d(cfg.max_h, cfg.max_w);
     const int B = cfg.max_batch;
     const size_t ny = (size_t)d.Hy * d.Wy * M;
-    const size_t nz = kind == 1 ? (size_t)d.Hz * d.Wz * N : 0;
+    const size_t nz = kind >= 1 ? (size_t)d.Hz * d.Wz * N : 0;
     const size_t img = (size_t)3 * cfg.max_h * cfg.max_w;
     const size_t scratch = scratch_bytes(ny, nz);
     const size_t bits = header_size(kind, kMaxSlices) + scratch;
@@ -92,12 +109,17 @@ int Codec::start()
         s.h_sym_y = (int8_t*)host_alloc(B * ny);
         s.d_sym_y = (int8_t*)dev_alloc(B * ny);
         if (!s.h_sym_y || !s.d_sym_y) return fail("slot y");
-        if (kind == 1) {
+        if (kind >= 1) {
             s.h_sym_z = (int8_t*)host_alloc(B * nz);
             s.d_sym_z = (int8_t*)dev_alloc(B * nz);
             s.h_idx = (uint8_t*)host_alloc(B * ny);
             s.d_idx = (uint8_t*)dev_alloc(B * ny);
             if (!s.h_sym_z || !s.d_sym_z || !s.h_idx || !s.d_idx) return fail("slot z/idx");
+        }
+        if (kind == 2) {
+            s.d_zc = (float*)dev_alloc(B * ny * 4 * sizeof(float));
+            s.d_mu = (float*)dev_alloc(B * ny * sizeof(float));
+            if (!s.d_zc || !s.d_mu) return fail("slot context");
         }
         s.h_scratch = (uint8_t*)host_alloc(B * scratch);
         s.scratch_per_frame = scratch;
@@ -109,7 +131,7 @@ int Codec::start()
         void* p = nullptr;
         if (hipHostGetDevicePointer(&p, s.h_sym_y, 0) != hipSuccess) return fail("mapped y");
         s.dm_sym_y = (int8_t*)p;
-        if (kind == 1) {
+        if (kind >= 1) {
             if (hipHostGetDevicePointer(&p, s.h_idx, 0) != hipSuccess) return fail("mapped idx");
             s.dm_idx = (uint8_t*)p;
         }
@@ -136,10 +158,20 @@ int Codec::start()
             sc.y = (float*)dev_alloc(nY * sizeof(float));
             if (!sc.y) return fail("stage scratch");
         }
-        if (kind == 1 && g <= 1) {
+        if (kind >= 1 && g <= 1) {
             sc.h1 = (float*)dev_alloc(nH1 * sizeof(float));
             sc.h2 = (float*)dev_alloc(nH2 * sizeof(float));
             if (!sc.h1 || !sc.h2) return fail("stage scratch");
+        }
+        if (kind == 2) {
+            const size_t pl = (size_t)B * d.Hy * d.Wy;
+            if (g <= 1) {
+                sc.e1 = (float*)dev_alloc(pl * layers[LIC_EP0A].co * sizeof(float));
+                sc.e2 = (float*)dev_alloc(pl * layers[LIC_EP1A].co * sizeof(float));
+                if (!sc.e1 || !sc.e2) return fail("stage scratch");
+            }
+            sc.yh = (float*)dev_alloc(nY * sizeof(float));
+            if (!sc.yh) return fail("stage scratch");
         }
     }
     if (cfg.hbm_budget_bytes && dev_bytes > cfg.hbm_budget_bytes) {
@@ -275,8 +307,10 @@ void Codec::gpu_loop(int gi)
             const long f0 = gs_frames.fetch_add(t->nb);
             t->judge = f0 % judge_every == 0 || f0 % judge_every + t->nb > judge_every;
         }
-        int (Codec::*body)(Task*, GpuStage&) =
-            G.kind == ST_GPU_ENC ? &Codec::gpu_encode : G.kind == ST_GPU_HS ? &Codec::gpu_hs : &Codec::gpu_gs;
+        const StageKind sk = t->route->stages[t->stage];
+        int (Codec::*body)(Task*, GpuStage&) = sk == ST_GPU_ENC ? &Codec::gpu_encode
+                                               : sk == ST_GPU_HS ? &Codec::gpu_hs
+                                               : sk == ST_GPU_CTX ? &Codec::gpu_ctx : &Codec::gpu_gs;
         if (!t->call && cfg.use_graphs) {
             // serving: request buffers in and out around a per-(stage, size,
             // batch, slot) graph that only touches pool buffers
@@ -349,6 +383,30 @@ int Codec::gpu_encode(Task* t, GpuStage& G)
     LAUNCH(LIC_GA0, x, sc.a, nullptr, st);
     LAUNCH(LIC_GA1, sc.a, sc.b, nullptr, st);
     LAUNCH(LIC_GA2, sc.b, sc.a, nullptr, st);
+    if (kind == 2) {
+        // context model: y's symbols come from the two checkerboard passes
+        // (quantised around the means), which write them checkerboard-major
+        // into device buffers
+        LAUNCH(LIC_GA3, sc.a, sc.y, s.d_sym_y, st);
+        LAUNCH(LIC_HA0, sc.y, sc.h1, nullptr, st);
+        LAUNCH(LIC_HA1, sc.h1, sc.h2, nullptr, st);
+        LAUNCH(LIC_HA2, sc.h2, nullptr, s.d_sym_z, st);
+        LAUNCH(LIC_HS0, s.d_sym_z, sc.h2, nullptr, st);
+        LAUNCH(LIC_HS1, sc.h2, sc.h1, nullptr, st);
+        LAUNCH(LIC_HS2, sc.h1, s.d_zc, nullptr, st);
+        HIP_OK(launch_cb_fill(s.d_zc, t->nb, d.Hy, d.Wy, 4 * M, 2 * M, 2 * M, 0, 0.0f, st));
+        LAUNCH(LIC_EP0A, s.d_zc, sc.e1, nullptr, st);
+        LAUNCH(LIC_EP1A, sc.e1, sc.e2, nullptr, st);
+        LAUNCH2(LIC_EP2A, sc.e2, s.d_idx, s.d_sym_y, sc.y, sc.yh, st);
+        LAUNCH(LIC_CX, sc.yh, s.d_zc, nullptr, st);
+        LAUNCH(LIC_EP0N, s.d_zc, sc.e1, nullptr, st);
+        LAUNCH(LIC_EP1N, sc.e1, sc.e2, nullptr, st);
+        LAUNCH2(LIC_EP2N, sc.e2, s.d_idx, s.d_sym_y, sc.y, sc.yh, st);
+        HIP_OK(hipMemcpyAsync(s.h_sym_z, s.d_sym_z, nz, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(s.h_idx, s.d_idx, ny, hipMemcpyDeviceToHost, st));
+        HIP_OK(hipMemcpyAsync(s.h_sym_y, s.d_sym_y, ny, hipMemcpyDeviceToHost, st));
+        return LIC_OK;
+    }
     LAUNCH(LIC_GA3, sc.a, kind == 1 ? sc.y : nullptr, zc ? (void*)s.dm_sym_y : (void*)s.d_sym_y, st);
     if (kind == 1) {
         LAUNCH(LIC_HA0, sc.y, sc.h1, nullptr, st);
@@ -376,8 +434,42 @@ int Codec::gpu_hs(Task* t, GpuStage& G)
     HIP_OK(hipMemcpyAsync(s.d_sym_z, s.h_sym_z, nz, hipMemcpyHostToDevice, st));
     LAUNCH(LIC_HS0, s.d_sym_z, sc.h2, nullptr, st);
     LAUNCH(LIC_HS1, sc.h2, sc.h1, nullptr, st);
+    if (kind == 2) {
+        // psi, then the anchors' means and indices (the pass that needs z only)
+        LAUNCH(LIC_HS2, sc.h1, s.d_zc, nullptr, st);
+        HIP_OK(launch_cb_fill(s.d_zc, t->nb, d.Hy, d.Wy, 4 * M, 2 * M, 2 * M, 0, 0.0f, st));
+        LAUNCH(LIC_EP0A, s.d_zc, sc.e1, nullptr, st);
+        LAUNCH(LIC_EP1A, sc.e1, sc.e2, nullptr, st);
+        LAUNCH2(LIC_EP2A, sc.e2, s.d_idx, nullptr, nullptr, s.d_mu, st);
+        const size_t half = (size_t)d.Hy * d.Wy * M / 2;
+        for (int b = 0; b < t->nb; ++b)
+            HIP_OK(hipMemcpyAsync(s.h_idx + 2 * b * half, s.d_idx + 2 * b * half, half, hipMemcpyDeviceToHost, st));
+        return LIC_OK;
+    }
     LAUNCH(LIC_HS2, sc.h1, zc ? (void*)s.dm_idx : (void*)s.d_idx, nullptr, st);
     if (!zc) HIP_OK(hipMemcpyAsync(s.h_idx, s.d_idx, ny, hipMemcpyDeviceToHost, st));
+    return LIC_OK;
+}
+
+// Context model, decoder: with the anchors decoded, their y_hat gives the
+// context of the other positions, whose means and indices follow.
+int Codec::gpu_ctx(Task* t, GpuStage& G)
+{
+    const FrameDims& d = t->route->dims;
+    Slot& s = slots[t->slot];
+    StageScratch& sc = G.scratch;
+    hipStream_t st = G.stream;
+    const size_t half = (size_t)d.Hy * d.Wy * M / 2;
+    for (int b = 0; b < t->nb; ++b)
+        HIP_OK(hipMemcpyAsync(s.d_sym_y + 2 * b * half, s.h_sym_y + 2 * b * half, half, hipMemcpyHostToDevice, st));
+    HIP_OK(launch_cb_dequant(s.d_sym_y, s.d_mu, sc.yh, nullptr, t->nb, d.Hy, d.Wy, M, 0, st));
+    LAUNCH(LIC_CX, sc.yh, s.d_zc, nullptr, st);
+    LAUNCH(LIC_EP0N, s.d_zc, sc.e1, nullptr, st);
+    LAUNCH(LIC_EP1N, sc.e1, sc.e2, nullptr, st);
+    LAUNCH2(LIC_EP2N, sc.e2, s.d_idx, nullptr, nullptr, s.d_mu, st);
+    for (int b = 0; b < t->nb; ++b)
+        HIP_OK(hipMemcpyAsync(s.h_idx + (2 * b + 1) * half, s.d_idx + (2 * b + 1) * half, half,
+                              hipMemcpyDeviceToHost, st));
     return LIC_OK;
 }
 
@@ -391,7 +483,22 @@ int Codec::gpu_gs(Task* t, GpuStage& G)
     const size_t fsz = (size_t)3 * d.H * d.W;
     const bool dev = t->route->is_device != 0;
     const bool direct = !t->staged && dev && t->call && frames_contiguous(t, fsz, true);
-    HIP_OK(hipMemcpyAsync(s.d_sym_y, s.h_sym_y, ny, hipMemcpyHostToDevice, st));
+    const void* gs_in = s.d_sym_y;
+    if (kind == 2) {
+        // the second pass's symbols join the anchors' (already on the
+        // device); y_hat = sym + mean in g_s's input type
+        const size_t half = ny / t->nb / 2;
+        for (int b = 0; b < t->nb; ++b)
+            HIP_OK(hipMemcpyAsync(s.d_sym_y + (2 * b + 1) * half, s.h_sym_y + (2 * b + 1) * half, half,
+                                  hipMemcpyHostToDevice, st));
+        const bool f32 = layers[LIC_GS0].dt == DT_F32;
+        for (int part = 0; part < 2; ++part)
+            HIP_OK(launch_cb_dequant(s.d_sym_y, s.d_mu, f32 ? sc.yh : nullptr, f32 ? nullptr : (void*)sc.yh, t->nb,
+                                     d.Hy, d.Wy, M, part, st));
+        gs_in = sc.yh;
+    } else {
+        HIP_OK(hipMemcpyAsync(s.d_sym_y, s.h_sym_y, ny, hipMemcpyHostToDevice, st));
+    }
     float* xo = direct ? t->xhats[0] : s.d_xhat;
     if (cfg.gs_mode != 0 && !distill) {
         t->fail(LIC_E_STATE, "no distilled synthesis transform loaded");
@@ -411,7 +518,7 @@ int Codec::gpu_gs(Task* t, GpuStage& G)
             if (rj != LIC_OK) return rj;
         }
     } else {
-        LAUNCH(LIC_GS0, s.d_sym_y, sc.a, nullptr, st);
+        LAUNCH(LIC_GS0, gs_in, sc.a, nullptr, st);
         LAUNCH(LIC_GS1, sc.a, sc.b, nullptr, st);
         LAUNCH(LIC_GS2, sc.b, sc.a, nullptr, st);
         LAUNCH(LIC_GS3, sc.a, xo, nullptr, st);
@@ -513,9 +620,9 @@ int Codec::load_distilled(const float* params, size_t n, float judge_psnr_db, in
 int Codec::cpu_parts(const Task* t, StageKind k) const
 {
     switch (k) {
-    case ST_CPU_ENC: return t->route->S + (kind == 1 ? 1 : 0);
+    case ST_CPU_ENC: return y_streams(kind, t->route->S) + (kind >= 1 ? 1 : 0);
     case ST_CPU_DEC_Z: return 1;
-    case ST_CPU_DEC_Y: return t->route->S;
+    case ST_CPU_DEC_Y: case ST_CPU_DEC_Y2: return t->route->S;
     default: return 0;
     }
 }
@@ -544,12 +651,28 @@ static inline void slice_rows(int Hy, int S, int s, int* r0, int* r1)
     *r1 = (int)((long)(s + 1) * Hy / S);
 }
 
-// Offset of y slice si (latent rows from r0) in a frame's rANS scratch: the
-// z stream's region comes first, then one region per slice, each 2 bytes per
-// symbol plus kStreamSlack.
-static inline size_t y_region(int kind, size_t nz, size_t row, int r0, int si)
+// y stream si of a frame: its symbols' offset and count in the frame's y
+// symbols (row = Wy M symbols per latent row).  Stream si is row slice si;
+// for the context model, slice si % S of set si / S (anchors, then the rest)
+// in the checkerboard-major layout, Wy M / 2 symbols per row of a set.
+static inline void y_span(int kind, size_t row, int Hy, int S, int si, size_t* off, size_t* cnt)
 {
-    return (kind == 1 ? 2 * nz + kStreamSlack : 0) + 2 * (size_t)r0 * row + kStreamSlack * (size_t)si;
+    const int set = kind == 2 ? si / S : 0, sl = kind == 2 ? si % S : si;
+    int r0, r1;
+    slice_rows(Hy, S, sl, &r0, &r1);
+    const size_t srow = kind == 2 ? row / 2 : row;
+    *off = (size_t)set * Hy * srow + (size_t)r0 * srow;
+    *cnt = (size_t)(r1 - r0) * srow;
+}
+
+// Offset of y stream si in a frame's rANS scratch: the z stream's region
+// comes first, then one region per stream, each 2 bytes per symbol plus
+// kStreamSlack.
+static inline size_t y_region(int kind, size_t nz, size_t row, int Hy, int S, int si)
+{
+    size_t off, cnt;
+    y_span(kind, row, Hy, S, si, &off, &cnt);
+    return (kind >= 1 ? 2 * nz + kStreamSlack : 0) + 2 * off + kStreamSlack * (size_t)si;
 }
 
 int Codec::cpu_job(Task* t, int b, int part)
@@ -559,32 +682,32 @@ int Codec::cpu_job(Task* t, int b, int part)
     const StageKind k = t->route->stages[t->stage];
     const int S = t->route->S;
     const size_t row = (size_t)d.Wy * M;
-    const size_t ny = (size_t)d.Hy * row, nz = kind == 1 ? (size_t)d.Hz * d.Wz * N : 0;
+    const size_t ny = (size_t)d.Hy * row, nz = kind >= 1 ? (size_t)d.Hz * d.Wz * N : 0;
     int8_t* sym_y = s.h_sym_y + (size_t)b * ny;        // frame b of the task (current size)
-    int8_t* sym_z = kind == 1 ? s.h_sym_z + (size_t)b * nz : nullptr;
-    const uint8_t* idx = kind == 1 ? s.h_idx + (size_t)b * ny : nullptr;
+    int8_t* sym_z = kind >= 1 ? s.h_sym_z + (size_t)b * nz : nullptr;
+    const uint8_t* idx = kind >= 1 ? s.h_idx + (size_t)b * ny : nullptr;
     uint8_t* scratch = s.h_scratch + (size_t)b * s.scratch_per_frame;
+    const bool gaussian = kind >= 1;                   // y coded with the scale-indexed tables
     if (k == ST_CPU_ENC) {
-        if (kind == 1 && part == 0) {
+        if (kind >= 1 && part == 0) {
             long len = lanes ? rans_ileave_encode_channel(lanes, sym_z, (long)nz, N, fact, scratch, 2 * nz + kStreamSlack)
                              : rans_encode_channel(sym_z, (long)nz, N, fact, scratch, 2 * nz + kStreamSlack);
             if (len < 0) { t->fail(LIC_E_STATE, "rANS z overflow"); return LIC_E_STATE; }
             t->part_len[b][0] = (size_t)len;
             return LIC_OK;
         }
-        const int si = part - (kind == 1 ? 1 : 0);
-        int r0, r1;
-        slice_rows(d.Hy, S, si, &r0, &r1);
-        uint8_t* region = scratch + y_region(kind, nz, row, r0, si);
-        const size_t cap = 2 * (size_t)(r1 - r0) * row + kStreamSlack;
-        const size_t off = (size_t)r0 * row, cnt = (size_t)(r1 - r0) * row;
+        const int si = part - (kind >= 1 ? 1 : 0);
+        size_t off, cnt;
+        y_span(kind, row, d.Hy, S, si, &off, &cnt);
+        uint8_t* region = scratch + y_region(kind, nz, row, d.Hy, S, si);
+        const size_t cap = 2 * cnt + kStreamSlack;
         long len;
         if (lanes)
-            len = kind == 1 ? rans_ileave_encode(lanes, sym_y + off, idx + off, (long)cnt, gauss, region, cap)
-                            : rans_ileave_encode_channel(lanes, sym_y + off, (long)cnt, M, fact, region, cap);
+            len = gaussian ? rans_ileave_encode(lanes, sym_y + off, idx + off, (long)cnt, gauss, region, cap)
+                           : rans_ileave_encode_channel(lanes, sym_y + off, (long)cnt, M, fact, region, cap);
         else
-            len = kind == 1 ? rans_encode(sym_y + off, idx + off, (long)cnt, gauss, region, cap)
-                            : rans_encode_channel(sym_y + off, (long)cnt, M, fact, region, cap);
+            len = gaussian ? rans_encode(sym_y + off, idx + off, (long)cnt, gauss, region, cap)
+                           : rans_encode_channel(sym_y + off, (long)cnt, M, fact, region, cap);
         if (len < 0) { t->fail(LIC_E_STATE, "rANS y overflow"); return LIC_E_STATE; }
         t->part_len[b][part] = (size_t)len;
         return LIC_OK;
@@ -598,19 +721,19 @@ int Codec::cpu_job(Task* t, int b, int part)
         }
         return LIC_OK;
     }
-    if (k == ST_CPU_DEC_Y) {
-        int r0, r1;
-        slice_rows(d.Hy, S, part, &r0, &r1);
-        const size_t off = (size_t)r0 * row, cnt = (size_t)(r1 - r0) * row;
+    if (k == ST_CPU_DEC_Y || k == ST_CPU_DEC_Y2) {
+        const int si = (k == ST_CPU_DEC_Y2 ? S : 0) + part;
+        size_t off, cnt;
+        y_span(kind, row, d.Hy, S, si, &off, &cnt);
         int rc;
         if (lanes)
-            rc = kind == 1 ? rans_ileave_decode(lanes, t->yp[b][part], t->ylen[b][part], idx + off, (long)cnt, gauss,
-                                                sym_y + off)
-                           : rans_ileave_decode_channel(lanes, t->yp[b][part], t->ylen[b][part], (long)cnt, M, fact,
-                                                        sym_y + off);
+            rc = gaussian ? rans_ileave_decode(lanes, t->yp[b][si], t->ylen[b][si], idx + off, (long)cnt, gauss,
+                                               sym_y + off)
+                          : rans_ileave_decode_channel(lanes, t->yp[b][si], t->ylen[b][si], (long)cnt, M, fact,
+                                                       sym_y + off);
         else
-            rc = kind == 1 ? rans_decode(t->yp[b][part], t->ylen[b][part], idx + off, (long)cnt, gauss, sym_y + off)
-                           : rans_decode_channel(t->yp[b][part], t->ylen[b][part], (long)cnt, M, fact, sym_y + off);
+            rc = gaussian ? rans_decode(t->yp[b][si], t->ylen[b][si], idx + off, (long)cnt, gauss, sym_y + off)
+                          : rans_decode_channel(t->yp[b][si], t->ylen[b][si], (long)cnt, M, fact, sym_y + off);
         if (rc != 0) {
             t->fail(LIC_E_CORRUPT, "corrupt y stream");
             return LIC_E_CORRUPT;
@@ -629,7 +752,8 @@ int Codec::cpu_finalize(Task* t, StageKind k)
     const int S = t->route->S;
     Slot& s = slots[t->slot];
     const size_t row = (size_t)d.Wy * M;
-    const size_t nz = kind == 1 ? (size_t)d.Hz * d.Wz * N : 0;
+    const size_t nz = kind >= 1 ? (size_t)d.Hz * d.Wz * N : 0;
+    const int ns = y_streams(kind, S);
     StreamHeader h;
     h.kind = kind;
     h.hs_exp = hs_exp;
@@ -641,11 +765,11 @@ int Codec::cpu_finalize(Task* t, StageKind k)
     h.N = N;
     h.M = M;
     h.model_id = model_id;
-    const int y0 = kind == 1 ? 1 : 0;
+    const int y0 = kind >= 1 ? 1 : 0;
     for (int b = 0; b < t->nb; ++b) {
-        uint32_t ylen[kMaxSlices];
-        size_t total = header_size(kind, S) + (kind == 1 ? t->part_len[b][0] : 0);
-        for (int i = 0; i < S; ++i) {
+        uint32_t ylen[2 * kMaxSlices];
+        size_t total = header_size(kind, S) + (kind >= 1 ? t->part_len[b][0] : 0);
+        for (int i = 0; i < ns; ++i) {
             ylen[i] = (uint32_t)t->part_len[b][y0 + i];
             total += ylen[i];
         }
@@ -655,18 +779,16 @@ int Codec::cpu_finalize(Task* t, StageKind k)
         }
         uint8_t* bits = s.h_bits + (size_t)b * s.bits_per_frame;
         const uint8_t* scratch = s.h_scratch + (size_t)b * s.scratch_per_frame;
-        write_header(bits, h, kind == 1 ? (uint32_t)t->part_len[b][0] : 0, ylen);
+        write_header(bits, h, kind >= 1 ? (uint32_t)t->part_len[b][0] : 0, ylen);
         uint8_t* p = bits + header_size(kind, S);
-        if (kind == 1) {
+        if (kind >= 1) {
             memcpy(p, scratch, t->part_len[b][0]);
             t->zp[b] = p;
             t->zlen[b] = t->part_len[b][0];
             p += t->part_len[b][0];
         }
-        for (int i = 0; i < S; ++i) {
-            int r0, r1;
-            slice_rows(d.Hy, S, i, &r0, &r1);
-            const uint8_t* region = scratch + y_region(kind, nz, row, r0, i);
+        for (int i = 0; i < ns; ++i) {
+            const uint8_t* region = scratch + y_region(kind, nz, row, d.Hy, S, i);
             memcpy(p, region, ylen[i]);
             t->yp[b][i] = p;
             t->ylen[b][i] = ylen[i];
