@@ -39,13 +39,27 @@ PEAK_BASIS = {"f32": "FP32 matrix cores", "bf16": "bf16 matrix cores", "fp8": "f
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_2208_01641_amd", "csrc", "conv_kernels.hip")
 LAYERS = ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", "GS0", "GS1", "GS2", "GS3")
+# the context model's layers beyond those (context convolution, entropy
+# parameters of the anchor pass and of the second pass)
+CTX_LAYERS = ("CX", "EP0A", "EP1A", "EP2A", "EP0N", "EP1N", "EP2N")
 
 
-def layer_flops(layer, H, W, N, M):
+def layer_flops(layer, H, W, N, M, kind=1):
     """Algorithmic FLOPs (2 x MAC) of one layer on one frame, on the
-    64-multiple padded frame the method codes (GDN contraction included)."""
+    64-multiple padded frame the method codes (GDN contraction included).
+    Context model (kind 2): h_s's last layer has 2M outputs; the context
+    convolution has 12 taps at half the latent positions; the entropy-
+    parameter layers run at half the positions each, the first on 4M inputs."""
     Hp, Wp = 64 * math.ceil(H / 64), 64 * math.ceil(W / 64)
     Hy, Wy = Hp // 16, Wp // 16
+    E1, E2 = 32 * round(10 * M / 96), 32 * round(8 * M / 96)
+    half = Hy * Wy // 2
+    ctx = {"CX": (half, M, 2 * M, 12), "EP0A": (half, 4 * M, E1, 1), "EP0N": (half, 4 * M, E1, 1),
+           "EP1A": (half, E1, E2, 1), "EP1N": (half, E1, E2, 1), "EP2A": (half, E2, 2 * M, 1),
+           "EP2N": (half, E2, 2 * M, 1), "HS2": (Hy * Wy, N, 2 * M, 9)}
+    if kind == 2 and layer in ctx:
+        c = ctx[layer]
+        return 2.0 * c[0] * c[1] * c[2] * c[3]
     conv = {  # (output pixels, or input pixels for transposed convs, C_in, C_out, k*k)
         "GA0": (Hp // 2 * Wp // 2, 3, N, 25), "GA1": (Hp // 4 * Wp // 4, N, N, 25),
         "GA2": (Hp // 8 * Wp // 8, N, N, 25), "GA3": (Hy * Wy, N, M, 25),
@@ -249,7 +263,7 @@ def run_workload(*, H, W, N, M, precision, batch, steps, warmup, threads, inflig
         ms, n = codec.layer_time(L)
         if n:
             per_launch = ms / n
-            flops = layer_flops(L, H, W, N, M) * batch      # a launch covers one task of `batch` frames
+            flops = layer_flops(L, H, W, N, M, kind) * batch      # a launch covers one task of `batch` frames
             layers[L] = {"avg_us": 1e3 * per_launch, "launches": n, "tflops": flops / (per_launch * 1e-3) / 1e12,
                          "flops_per_launch": flops, "form": codec.layer_kernel(L, H, W)[0]}
     if mode == "enc":                     # reconstructions of the encoded frames, untimed
@@ -653,6 +667,20 @@ def main():
                                   **dict(common, timed_layers=list(LAYERS)))
         var["fp32_720p_1dn_one_frame_in_flight"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms")})
         var["fp32_720p_1dn_one_frame_in_flight"]["layers_us"] = {L: round(v["avg_us"], 1) for L, v in r["layers"].items()}
+        # the context model (checkerboard-parallel context prediction) at
+        # 720p: encode chained into decode, pipelined, in both of its forms;
+        # and one frame in flight with the kernel time of every layer
+        for name, p in (("fp32", 0), ("bf16", 1)):
+            r, _, _, _ = run_workload(precision=p, steps=150, warmup=15, inflight=args.inflight, kind=2, **hd,
+                                      **common)
+            var[f"{name}_720p_context"] = _round({k: r[k] for k in keys})
+        r, _, _, _ = run_workload(precision=0, steps=30, warmup=5, inflight=1, kind=2, **hd,
+                                  **dict(common, timed_layers=list(LAYERS) + list(CTX_LAYERS)))
+        v = _round({k: r[k] for k in keys})
+        v["gpu_kernel_ms_per_frame"] = round(r["kernel_ms_per_frame"], 4)
+        v["layers_us"] = {L: round(x["avg_us"], 1) for L, x in r["layers"].items()}
+        v["layers_tflops"] = {L: round(x["tflops"], 1) for L in CTX_LAYERS for x in [r["layers"].get(L)] if x}
+        var["fp32_720p_context_one_frame_in_flight"] = v
         big = {}
         for name, p in (("fp32", 0), ("bf16", 1), ("fp8", 2)):
             r, _, _, _ = run_workload(H=1080, W=1920, N=192, M=320, precision=p, batch=4, steps=40, warmup=8,
