@@ -256,3 +256,27 @@ def test_context_codec_720p_sampled(torch_dev):
     c.run_layer("GS3", 1, H, W, a2, xg)
     assert torch.equal(xh, xg)
     c.close()
+
+
+def test_context_codec_batches_equal_single_frames(torch_dev):
+    """Tasks of two frames (one launch per layer for both) give every frame
+    the bits and pixels it gets alone: the per-frame copies of the two
+    checkerboard sets and the batched kernels keep frames apart."""
+    torch = torch_dev
+    H, W = 200, 328
+    xs = torch.from_numpy(np.stack([synth.frame_sinusoid(H, W, t=t) for t in (1, 2, 3)])).cuda()
+    c1, _ = make_codec(2, N, M, max_h=H, max_w=W, y_slices=2, entropy_threads=4, max_in_flight=2, max_batch=1)
+    c2, _ = make_codec(2, N, M, max_h=H, max_w=W, y_slices=2, entropy_threads=4, max_in_flight=2, max_batch=2)
+    b1 = c1.encode(xs)
+    b2 = c2.encode(xs)
+    assert b1 == b2
+    x1 = torch.empty_like(xs)
+    x2 = torch.empty_like(xs)
+    c1.decode(b1, x1)
+    c2.decode(b2, x2)
+    assert torch.equal(x1, x2)
+    x3 = torch.empty_like(xs)
+    assert c2.encode_decode(xs, x3) == b1
+    assert torch.equal(x3, x1)
+    c1.close()
+    c2.close()
