@@ -42,6 +42,7 @@ LAYERS = ("GA0", "GA1", "GA2", "GA3", "HA0", "HA1", "HA2", "HS0", "HS1", "HS2", 
 # the context model's layers beyond those (context convolution, entropy
 # parameters of the anchor pass and of the second pass)
 CTX_LAYERS = ("CX", "EP0A", "EP1A", "EP2A", "EP0N", "EP1N", "EP2N")
+CODEC_NAME = {0: "factorized-prior", 1: "scale-hyperprior", 2: "context-model (checkerboard) mean-scale hyperprior"}
 
 
 def layer_flops(layer, H, W, N, M, kind=1):
@@ -519,6 +520,9 @@ def main():
     ap.add_argument("--rans-lanes", type=int, default=8,
                     help="entropy coder: interleaved rANS states (0: byte-wise single-state rANS)")
     ap.add_argument("--serial", action="store_true", help="one frame in flight (unpipelined)")
+    ap.add_argument("--kind", type=int, choices=[0, 1, 2], default=1,
+                    help="codec of the main workload: 1 scale hyperprior (the metric's), 0 factorized prior, "
+                         "2 context model (for profiles of those codecs)")
     ap.add_argument("--all-layers", action="store_true", help="time every layer (per-layer breakdown)")
     ap.add_argument("--no-variants", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -551,11 +555,13 @@ def main():
     N, M = 128, 192
     # (the headline run times two layers only: events between every launch
     # perturb the pipelined run; the one-frame-in-flight variant times all)
-    timed = list(LAYERS) if args.all_layers else ["GA1", "GS2"]
+    timed = ["GA1", "GS2"]
+    if args.all_layers:
+        timed = [L for L in LAYERS if args.kind or not L.startswith("H")] + (list(CTX_LAYERS) if args.kind == 2 else [])
     main_res, x0, P, blob = run_workload(
         H=H, W=W, N=N, M=M, precision=prec, batch=1, steps=K, warmup=Wm, threads=threads,
         inflight=1 if args.serial else args.inflight, slices=args.slices, zero_copy=args.zero_copy,
-        timed_layers=timed, copy_probe_mib=args.copy_probe_mib)
+        timed_layers=timed, copy_probe_mib=args.copy_probe_mib, kind=args.kind)
 
     per_layer = main_res["layers"]
     dom = max(per_layer, key=lambda L: per_layer[L]["avg_us"] * per_layer[L]["launches"])
@@ -564,7 +570,8 @@ def main():
     ach = per_layer[dom]["tflops"]
     roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4),
-                "traffic": traffic_for(dom, args.precision) if (H, W, N, M) == (720, 1280, 128, 192) else None,
+                "traffic": (traffic_for(dom, args.precision)
+                            if (H, W, N, M, args.kind) == (720, 1280, 128, 192, 1) else None),
                 "kernel": dom, "form": form, "peak_basis": PEAK_BASIS[form],
                 "avg_us": round(per_layer[dom]["avg_us"], 2),
                 "flops_per_launch": per_layer[dom]["flops_per_launch"]}
@@ -582,7 +589,7 @@ def main():
         "vs_baseline": None,
         "dtype": dtype,
         "data": "synthetic",
-        "config": {"workload": f"scale-hyperprior N={N} M={M} {args.precision.upper()} encode chained into decode, "
+        "config": {"workload": f"{CODEC_NAME[args.kind]} N={N} M={M} {args.precision.upper()} encode chained into decode, "
                                f"3x{H}x{W} frames (32 moving sinusoids + noise), pipelined",
                    "frames": K, "entropy_threads": threads, "max_in_flight": 1 if args.serial else args.inflight,
                    "y_slices": args.slices, "zero_copy": args.zero_copy, "rans_lanes": args.rans_lanes},
