@@ -65,7 +65,9 @@ typedef struct {
                                /* passes (the parallel context prediction Sections   */
                                /* II and VII point to; N=128 M=192, FP32 or BF16     */
                                /* form, full g_s, no serving; its h_a / h_s, context */
-                               /* and entropy-parameter layers run in FP32)          */
+                               /* and entropy-parameter layers run in FP32; its      */
+                               /* symbols and indices go through device buffers and  */
+                               /* copies whatever zero_copy says)                    */
     int32_t  N, M;             /* transform / latent channels (128/192 or 192/320)   */
     int32_t  precision;        /* LIC_PREC_FP32, _BF16 or _FP8: g_a / g_s GEMM       */
                                /* operands and their activations in bf16, or in OCP  */

@@ -113,7 +113,7 @@ def _check_pass(m, L, part, psi, ctx, y):
     mu, sraw = oracle.entropy_parameters(m.P, psi, ctx)
     # indices (the scale decision) and symbols (the rounding of y - mean)
     ig = np.transpose(_cb(L["idx"], part), (2, 0, 1)).astype(np.int32)
-    n_i, ok = index_mismatches(ig, np.transpose(_take(oracle.scales_from_hs(sraw, 1), part), (2, 0, 1)), m.t)
+    n_i, ok = index_mismatches(ig, np.transpose(_take(oracle.scales_from_hs(sraw, m.hs_out), part), (2, 0, 1)), m.t)
     assert ok, f"pass {part}: {n_i} index mismatches outside the band"
     sg = np.transpose(_cb(L["sym"], part), (2, 0, 1)).astype(np.int32)
     n_s, ok = boundary_mismatches(sg, np.transpose(_take(y, part), (2, 0, 1)),
@@ -167,11 +167,12 @@ def test_context_layers_match_oracle(torch_dev, H, W):
     c.close()
 
 
-@pytest.mark.parametrize("H,W,S,lanes,prec", [(128, 192, 2, 0, 0), (200, 328, 3, 8, 0), (200, 328, 2, 8, 1)])
-def test_context_codec(torch_dev, H, W, S, lanes, prec):
+@pytest.mark.parametrize("H,W,S,lanes,prec,hs_out", [(128, 192, 2, 0, 0, 1), (200, 328, 3, 8, 0, 1),
+                                                     (200, 328, 2, 8, 1, 1), (136, 200, 2, 0, 0, 0)])
+def test_context_codec(torch_dev, H, W, S, lanes, prec, hs_out):
     torch = torch_dev
     c, m = make_codec(2, N, M, max_h=H, max_w=W, y_slices=S, entropy_threads=4, max_in_flight=3,
-                      rans_lanes=lanes, precision=prec)
+                      rans_lanes=lanes, precision=prec, hs_out=hs_out)
     x = synth.frame_sinusoid(H, W, t=7)
     xd = torch.from_numpy(x)[None].cuda()
     bits = c.encode(xd)[0]
@@ -208,7 +209,7 @@ def test_context_codec(torch_dev, H, W, S, lanes, prec):
     zg = L["sym_z"][0].cpu().numpy()
     psi64 = m.h_s(np.transpose(zg, (2, 0, 1)).astype(np.float64) + m.medians[:, None, None].astype(np.float64))
     mu1, s1 = oracle.entropy_parameters(m.P, psi64, np.zeros_like(psi64))
-    same = np.array_equal(_cb(L["idx"], 0), _take(oracle.scale_index(oracle.scales_from_hs(s1, 1), m.t), 0))
+    same = np.array_equal(_cb(L["idx"], 0), _take(oracle.scale_index(oracle.scales_from_hs(s1, m.hs_out), m.t), 0))
     if same:
         Hy, Wy = mu1.shape[1:]
         s_a = np.zeros((Hy, Wy, M))
@@ -216,7 +217,7 @@ def test_context_codec(torch_dev, H, W, S, lanes, prec):
         A = oracle.checkerboard(Hy, Wy)[None]
         ctx64 = oracle.context(np.where(A, np.transpose(s_a, (2, 0, 1)) + mu1, 0.0), m.P["cx.w"], m.P["cx.b"])
         _, s2 = oracle.entropy_parameters(m.P, psi64, ctx64)
-        same = np.array_equal(_cb(L["idx"], 1), _take(oracle.scale_index(oracle.scales_from_hs(s2, 1), m.t), 1))
+        same = np.array_equal(_cb(L["idx"], 1), _take(oracle.scale_index(oracle.scales_from_hs(s2, m.hs_out), m.t), 1))
     if same:
         xr_o, dd = m.decode(bits)
         for part in (0, 1):
