@@ -675,9 +675,9 @@ def main():
         var["fp32_720p_1dn_one_frame_in_flight"] = _round({k: r[k] for k in ("fps", "p50_ms", "p99_ms")})
         var["fp32_720p_1dn_one_frame_in_flight"]["layers_us"] = {L: round(v["avg_us"], 1) for L, v in r["layers"].items()}
         # the context model (checkerboard-parallel context prediction) at
-        # 720p: encode chained into decode, pipelined, in both of its forms;
+        # 720p: encode chained into decode, pipelined, in every form;
         # and one frame in flight with the kernel time of every layer
-        for name, p in (("fp32", 0), ("bf16", 1)):
+        for name, p in (("fp32", 0), ("bf16", 1), ("fp8", 2)):
             r, _, _, _ = run_workload(precision=p, steps=150, warmup=15, inflight=args.inflight, kind=2, **hd,
                                       **common)
             var[f"{name}_720p_context"] = _round({k: r[k] for k in keys})

@@ -63,7 +63,7 @@ typedef struct {
                                /* whose entropy parameters also see a context of     */
                                /* decoded latents, in two parallel checkerboard      */
                                /* passes (the parallel context prediction Sections   */
-                               /* II and VII point to; N=128 M=192, FP32 or BF16     */
+                               /* II and VII point to; N=128 M=192, any precision   */
                                /* form, full g_s, no serving; its h_a / h_s, context */
                                /* and entropy-parameter layers run in FP32; its      */
                                /* symbols and indices go through device buffers and  */

@@ -92,8 +92,8 @@ int codec_create(const codec_config* cfg, const void* blob, size_t blob_len, cod
         return LIC_E_ARG;
     }
     if (cfg->hs_out != LIC_HS_EXP && cfg->hs_out != LIC_HS_RELU) { g_create_error = "bad hs_out"; return LIC_E_ARG; }
-    if (cfg->kind == LIC_KIND_CONTEXT && (cfg->precision == LIC_PREC_FP8 || cfg->gs_mode != 0)) {
-        g_create_error = "context model: FP32 or BF16 form with the full g_s";
+    if (cfg->kind == LIC_KIND_CONTEXT && cfg->gs_mode != 0) {
+        g_create_error = "context model: full g_s only";
         return LIC_E_ARG;
     }
     if (cfg->gs_mode < 0 || cfg->gs_mode > 2) { g_create_error = "gs_mode must be 0, 1 or 2"; return LIC_E_ARG; }

@@ -68,7 +68,22 @@ __global__ void cb_dequant_kernel(const int8_t* __restrict__ sym, const float* _
     }
 }
 
+__global__ void f32_to_bf16_kernel(const float* __restrict__ in, __hip_bfloat16* __restrict__ out, long n)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = __float2bfloat16(in[i]);
+}
+
 }  // namespace
+
+hipError_t launch_f32_to_bf16(const float* in, void* out, long n, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    const int threads = 256;
+    hipLaunchKernelGGL(f32_to_bf16_kernel, dim3((unsigned)((n + threads - 1) / threads)), dim3(threads), 0, s, in,
+                       static_cast<__hip_bfloat16*>(out), n);
+    return hipGetLastError();
+}
 
 hipError_t launch_cb_fill(float* buf, int n, int Hy, int Wy, int ld, int off, int C, int part, float value,
                           hipStream_t s)

@@ -30,6 +30,8 @@ hipError_t launch_conv(const KernelKey& k, const ConvArgs& args, int nblocks, hi
 // float32 (out32) and / or bf16 (out16), either may be null.
 hipError_t launch_cb_fill(float* buf, int n, int Hy, int Wy, int ld, int off, int C, int part, float value,
                           hipStream_t s);
+// bf16 (round to nearest even) copy of n floats.
+hipError_t launch_f32_to_bf16(const float* in, void* out, long n, hipStream_t s);
 hipError_t launch_cb_dequant(const int8_t* sym, const float* mean, float* out32, void* out16, int n, int Hy, int Wy,
                              int C, int part, hipStream_t s);
 

@@ -328,9 +328,17 @@ int Codec::calibrate_fp8(const float* x, int n, int H, int W)
     };
     if ((rc = step(LIC_GA0, x, buf[1], nullptr)) == LIC_OK && (rc = step(LIC_GA1, buf[1], buf[2], nullptr)) == LIC_OK &&
         (rc = step(LIC_GA2, buf[2], buf[1], nullptr)) == LIC_OK &&
-        (rc = launch_layer(LIC_GA3, n, d, buf[1], buf[2], buf[3], layer_stream, &e)) == LIC_OK &&
-        (rc = step(LIC_GS0, buf[3], buf[1], nullptr)) == LIC_OK)
-        rc = step(LIC_GS1, buf[1], buf[2], nullptr);
+        (rc = launch_layer(LIC_GA3, n, d, buf[1], buf[2], buf[3], layer_stream, &e)) == LIC_OK) {
+        // the context model's g_s starts from y_hat = sym + mean in bf16; y
+        // itself (within half a step of it) stands in for the calibration
+        if (kind == 2) {
+            const hipError_t he = launch_f32_to_bf16(static_cast<const float*>(buf[2]), buf[3],
+                                                     (long)n * d.Hy * d.Wy * M, layer_stream);
+            if (he != hipSuccess) { err = "calibration: conversion failed"; rc = LIC_E_HIP; }
+        }
+        if (rc == LIC_OK && (rc = step(LIC_GS0, buf[3], buf[1], nullptr)) == LIC_OK)
+            rc = step(LIC_GS1, buf[1], buf[2], nullptr);
+    }
     if (rc != LIC_OK && err.empty()) err = e;
     if (hipStreamSynchronize(layer_stream) != hipSuccess && rc == LIC_OK) { err = "calibration failed"; rc = LIC_E_HIP; }
     for (void* b : buf) (void)hipFree(b);
@@ -419,7 +427,9 @@ int Codec::build_layers(const ParamMap& P)
         L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
         // the e4m3 form's image layer: bf16 operands (a K of 75 is one
         // chunk; pixel values keep 8 bits), e4m3 activations out
-        L.out_e4m3 = L.dt == DT_FP8 && sp.ld == LD_RGB;
+        // (so does the context model's first g_s layer, whose input y_hat =
+        // sym + mean arrives as bf16)
+        L.out_e4m3 = L.dt == DT_FP8 && (sp.ld == LD_RGB || (kind == 2 && sp.id == LIC_GS0));
         if (L.out_e4m3) L.dt = DT_BF16;
         // and its output layer too (bf16 halo tiles: the 3 output channels
         // make a K chunk of 128 (tap, channel) pairs a poor fit), fed by a
