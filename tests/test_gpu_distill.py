@@ -354,3 +354,67 @@ def test_serving_reload_of_the_distilled_net_drops_its_graphs(torch_dev):
                 assert torch.equal(got[i], ref[i]), (seed, rep, i)
     c.close_stream(sid)
     c.close()
+
+
+def test_trained_net_gains_decode_speed_at_a_bounded_fidelity_cost(torch_dev):
+    """What the distilled net gains over the method without it: the same
+    bitstreams decode faster (g_s is the decoder's largest GPU stage and the
+    net has about a twelfth of its FLOPs), and training on the full decoder's
+    own (y_hat, x_hat) pairs is what makes its output usable — fidelity to
+    the full g_s far above the untrained net's, and within 1 dB of the full
+    g_s's PSNR against the source."""
+    torch = torch_dev
+    import time
+
+    from gpu_util import make_codec
+    from paper_2208_01641_amd import Distill
+    from paper_2208_01641_amd import distill_train as dtr
+    H = W = 128
+    count, hold = 640, 64
+    teacher, _ = make_codec(1, 128, M, max_h=H, max_w=W, y_slices=1, entropy_threads=2, max_in_flight=1)
+    imgs = torch.from_numpy(np.stack([synth.frame_sinusoid(H, W, t=0, stream=10 ** 6 + i)
+                                      for i in range(count)])).cuda()
+    sym, rec = dtr.build_pairs(teacher, imgs)
+    teacher.close()
+    net = Distill(_params(seed=3), M, F, max_batch=32, max_hy=H // 16, max_wy=W // 16)
+    fid0, _ = dtr.evaluate(net, sym[-hold:], rec[-hold:], imgs[-hold:])
+    losses = dtr.train(net, sym[:-hold], rec[:-hold], steps=800, batch=32, seed=4)
+    fid1, gap1 = dtr.evaluate(net, sym[-hold:], rec[-hold:], imgs[-hold:])
+    print(f"held-out fidelity to the full g_s: untrained {fid0.mean():.2f} dB, trained {fid1.mean():.2f} dB; "
+          f"gap against the source {gap1.mean():+.3f} dB; loss {losses[:10].mean():.4f} -> {losses[-50:].mean():.4f}")
+    assert losses[-50:].mean() < 0.5 * losses[:10].mean()
+    assert fid1.mean() > fid0.mean() + 5.0
+    assert abs(gap1.mean()) < 1.0
+    params = net.get(0)
+    net.close()
+    # 720p decode of the same bitstreams with the full and the distilled g_s:
+    # the busy time of the decoder's g_s stage and the wall time
+    Hd, Wd, n = 720, 1280, 96
+    frames = synth.frames_sinusoid_torch(Hd, Wd, range(n), device="cuda")
+    times, busy, outs = {}, {}, {}
+    bits = None
+    for mode in (0, 1):
+        c, _ = make_codec(1, 128, M, max_h=Hd, max_w=Wd, y_slices=8, entropy_threads=16, max_in_flight=6,
+                          gs_mode=mode)
+        if mode:
+            c.load_distilled(params, judge_psnr_db=0.0, judge_every=1000)
+        bits = bits or c.encode(frames)
+        xr = torch.empty_like(frames)
+        c.decode(bits[:6], xr[:6])                      # warm-up
+        torch.cuda.synchronize()
+        b0 = c.stats()["gpu_busy_s"][2]
+        t0 = time.perf_counter()
+        c.decode(bits, xr)
+        torch.cuda.synchronize()
+        times[mode] = time.perf_counter() - t0
+        busy[mode] = c.stats()["gpu_busy_s"][2] - b0
+        outs[mode] = xr
+        c.close()
+    fid = 10 * np.log10(1.0 / float(torch.mean((outs[0] - outs[1]) ** 2)))
+    print(f"720p decode of {n} frames: full g_s {1e3 * times[0]:.1f} ms (g_s stage busy {1e3 * busy[0]:.1f} ms), "
+          f"distilled {1e3 * times[1]:.1f} ms ({1e3 * busy[1]:.1f} ms); PSNR(full, distilled) {fid:.2f} dB")
+    # the g_s stage's GPU work shrinks severalfold; the wall time less, since
+    # the other stages (entropy decoding on the host, h_s) remain
+    assert busy[1] < 0.5 * busy[0]
+    assert times[1] < 0.9 * times[0]
+    assert fid > fid0.mean() + 5.0
