@@ -291,3 +291,38 @@ def test_context_codec_batches_equal_single_frames(torch_dev):
     assert torch.equal(x3, x1)
     c1.close()
     c2.close()
+
+
+def test_context_codec_errors_leave_it_usable(torch_dev):
+    """Truncated streams, streams of another model and damaged anchor
+    payloads are refused (or, where the coder cannot tell, decoded to some
+    image) without harm: the next decode gives the right pixels."""
+    from paper_2208_01641_amd import LicError
+    torch = torch_dev
+    H, W = 128, 192
+    c, _ = make_codec(2, N, M, max_h=H, max_w=W, y_slices=2, entropy_threads=2, max_in_flight=2)
+    xd = torch.from_numpy(synth.frame_sinusoid(H, W, t=2))[None].cuda()
+    bits = c.encode(xd)[0]
+    good = torch.empty((1, 3, H, W), device="cuda")
+    c.decode([bits], good)
+    out = torch.empty_like(good)
+    with pytest.raises(LicError) as e:
+        c.decode([bits[:-3]], out)
+    assert e.value.code == -4                        # LIC_E_CORRUPT
+    c1, _ = make_codec(1, N, M, max_h=H, max_w=W, y_slices=2, entropy_threads=2)
+    with pytest.raises(LicError) as e:
+        c.decode([c1.encode(xd)[0]], out)
+    assert e.value.code == -8                        # LIC_E_MODEL (another kind)
+    c1.close()
+    hdr = oracle.parse_container(bits)
+    start = len(bits) - sum(len(y) for y in hdr["y"])     # first anchor slice
+    bad = bytearray(bits)
+    for i in range(start + 8, start + 40):
+        bad[i] ^= 0x5A
+    try:
+        c.decode([bytes(bad)], out)
+    except LicError as err:
+        assert err.code == -4
+    c.decode([bits], out)
+    assert torch.equal(out, good)
+    c.close()
