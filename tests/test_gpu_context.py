@@ -235,12 +235,13 @@ def test_context_codec(torch_dev, H, W, S, lanes, prec, hs_out):
     c.close()
 
 
-def test_context_codec_720p_sampled(torch_dev):
-    """The 720p kernels (their own tile shapes) against FP64 on the GPU's y:
-    every index and symbol of both passes within the bands, and the decoder
+@pytest.mark.parametrize("H,W", [(720, 1280), (1080, 1920)])
+def test_context_codec_720p_sampled(torch_dev, H, W):
+    """The full-size kernels (their own tile shapes: 720p and 1080p grids
+    choose other split-K configurations) against FP64 on the GPU's y: every
+    index and symbol of both passes within the bands, and the decoder
     reproduces the encoder's y_hat."""
     torch = torch_dev
-    H, W = 720, 1280
     c, m = make_codec(2, N, M, max_h=H, max_w=W, y_slices=8, entropy_threads=8, max_in_flight=2)
     xd = torch.from_numpy(synth.frame_sinusoid(H, W, t=11))[None].cuda()
     L = _encoder_chain(torch, c, xd, H, W)
