@@ -1064,7 +1064,8 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // count whatever the first guess.
     auto scale_count = [&](float y, const float* ts, float t0, float inv) __attribute__((always_inline)) {
         const float s = a.hs_exp ? y : fmaxf(fmaxf(y, 0.0f), t0);
-        const float u = a.hs_exp ? (s - t0) * inv : __log2f(s / t0) * inv;
+        // (the guess needs no exact division: the comparisons settle it)
+        const float u = a.hs_exp ? (s - t0) * inv : (__log2f(s) - __log2f(t0)) * inv;
         int e = (int)ceilf(fminf(fmaxf(u, 0.0f), 63.0f));     // NaN: 0
         while (e < 63 && ts[e] < s) ++e;
         while (e > 0 && !(ts[e - 1] < s)) --e;
@@ -1211,14 +1212,16 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
                 f4 y;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) {
-                    // GDN: x times the hardware reciprocal square root (within
-                    // about one ulp; n >= beta > 0), IGDN: x sqrt(n); 1DN: x
-                    // times the hardware reciprocal (about one ulp), inverse x n
+                    // GDN: x times the hardware reciprocal square root, IGDN:
+                    // x times the hardware square root (each within about one
+                    // ulp; n >= beta > 0; the correctly rounded sqrtf costs a
+                    // dozen more instructions per value); 1DN: x times the
+                    // hardware reciprocal (about one ulp), inverse x n
                     const float nv = nacc[mt][nt][i];
                     if (EP == EP_GDN)
                         y[i] = acc[mt][nt][i] * (a.norm1 ? __builtin_amdgcn_rcpf(nv) : __builtin_amdgcn_rsqf(nv));
                     else
-                        y[i] = acc[mt][nt][i] * (a.norm1 ? nv : sqrtf(nv));
+                        y[i] = acc[mt][nt][i] * (a.norm1 ? nv : __builtin_amdgcn_sqrtf(nv));
                 }
                 if (pv[nt]) store_act(obase[nt] + mt * 16 + kg * 4, y);
             }
