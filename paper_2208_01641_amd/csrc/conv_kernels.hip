@@ -179,8 +179,14 @@ __device__ __forceinline__ int xcd_logical_tile(int L, int T)
 // output tile and take interleaved K chunks; their partial sums are added in
 // LDS in the fixed wave order 0, 1, ..., KSPLIT-1, so results do not depend
 // on timing, batch size or which stream runs the kernel.
+// The split-FP32 kernels and the e4m3 GDN kernels with 8 row blocks on FP32
+// activations are built for two blocks (two waves per SIMD, 256 registers):
+// without the bound the compiler's split between VGPRs and accumulation
+// registers would take more than 256 in total.
 template <int TAG, int CIN, int MT, int NT, int WAVES, int KSPLIT, int LD, int EP, int DT>
-__global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(ConvArgs a)
+__global__ void __launch_bounds__(64 * WAVES,
+                                  DT == DT_F32X || (DT == DT_FP8 && WAVES == 4 && KSPLIT == 1 && MT <= 8 && LD == LD_F32) ? 2 : 1)
+conv_igemm(ConvArgs a)
 {
     using Frag = typename Prec<DT>::Frag;
     using Elem = typename Prec<DT>::Elem;
@@ -250,7 +256,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // one LDS buffer for the staged weight ring of the K loop and, after it,
     // the staged gamma slices of the GDN epilogue
     constexpr int kGP = (DT == DT_F32 || DT == DT_F32X) ? 3 : 2;   // bf16 parts of gamma
-    constexpr int kAWords = kALdsEarly ? 3 * MT * 16 * (DT == DT_FP8 ? 36 : 20) : kALdsX ? 2 * MT * 16 * 52
+    constexpr int kAWords = kALdsEarly ? (DT == DT_FP8 ? 2 * MT * 16 * 36 : 3 * MT * 16 * 20) : kALdsX ? 2 * MT * 16 * 52
                           : LD == LD_TILE ? 2 * ((WAVES + 2) * (NT * 16 + 2) + 9 * MT * 16) * 16 : 0;
     constexpr int kGWords = kGLds ? 2 * kGP * MT * 16 * 16 : 0;
     constexpr int kSmemWords = (kAWords > kGWords ? kAWords : kGWords) > 0 ? (kAWords > kGWords ? kAWords : kGWords) : 4;
@@ -673,9 +679,10 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
     // Shared weights (GDN layers, one pixel tile per wave, no split-K): the
     // four waves of a block need the same weight rows for every chunk, so the
     // block stages each chunk's weight tile in LDS once (two 16-byte pieces
-    // per thread) instead of every wave fetching it: a 3-stage LDS ring,
-    // filled two chunks ahead from registers loaded two chunks before that,
-    // one barrier per chunk.  The pixel operands keep their per-wave ring.
+    // per thread; e4m3: four) instead of every wave fetching it: a 3-stage
+    // LDS ring, filled two chunks ahead from registers loaded two chunks
+    // before that (e4m3: a 2-stage ring, below), one barrier per chunk.  The
+    // pixel operands keep their per-wave ring.
     constexpr bool kALds = kALdsEarly;
     if constexpr (kALds) {
         static_assert(P == 3, "the shared-weight loop is written for a 3-deep ring");
@@ -688,8 +695,8 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
         constexpr int ROWS = MT * 16;
         constexpr int NPIECE = ROWS * PPR / 256;            // pieces per thread per chunk
         static_assert(ROWS * PPR % 256 == 0, "whole pieces per thread");
-        uint32_t* const As = smem;                          // [3][ROWS][AROW]
-        static_assert(3 * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
+        uint32_t* const As = smem;                          // [stages][ROWS][AROW]
+        static_assert((DT == DT_FP8 ? 2 : 3) * ROWS * AROW <= kSmemWords, "weight ring fits the LDS buffer");
         const int tid = threadIdx.x;
         int a_t = 0, a_kc = 0, a_k = 0;
         auto a_gload = [&](u32x4 (&r)[NPIECE]) __attribute__((always_inline)) {
@@ -736,6 +743,55 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             if constexpr (DT == DT_FP8) loadB8(kk, B);
             else cursor_loadB(B);
         };
+      if constexpr (DT == DT_FP8) {
+        // e4m3: a two-stage ring, so that the kernel fits two waves per SIMD
+        // (the three-stage ring's register sets, with operands of 32 bytes
+        // per lane, need one wave per SIMD).  Chunk c sits in register set
+        // c % 2, LDS stage c % 2 and pixel buffer c % 2.  Step k issues the
+        // weight loads of chunk k + 2 (into the set of chunk k, stored one
+        // step earlier) and the pixel loads of chunk k + 1, multiplies chunk
+        // k, and stores chunk k + 1 (loaded at the start of step k - 1) into
+        // the stage chunk k - 1 used before the last barrier.
+        u32x4 ra[2][NPIECE];
+        BRaw Bp[2][NT];
+        if (0 < nk) a_gload(ra[0]);
+        if (1 < nk) a_gload(ra[1]);
+        if (0 < nk) loadBs(0, Bp[0]);
+        if (0 < nk) a_store(0, ra[0]);
+        __syncthreads();
+        auto step = [&](int k, auto jc, bool guard) __attribute__((always_inline)) {
+            constexpr int j = decltype(jc)::value;          // k % 2
+            if (!guard || k + 2 < nk) a_gload(ra[j]);
+            if (!guard || k + 1 < nk) loadBs(k + 1, Bp[1 - j]);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) {
+                const uint32_t* src = &As[(j * ROWS + mt * 16 + l16) * AROW + kg * (RB / 16)];
+                const u32x4 lo = *reinterpret_cast<const u32x4*>(src), hi = *reinterpret_cast<const u32x4*>(src + 4);
+                const Frag A = i32x8{(int)lo[0], (int)lo[1], (int)lo[2], (int)lo[3],
+                                     (int)hi[0], (int)hi[1], (int)hi[2], (int)hi[3]};
+#pragma unroll
+                for (int nt = 0; nt < NT; ++nt)
+                    acc[mt][nt] = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(
+                        A, Bp[j][nt], acc[mt][nt], 0, 0, 0, kE8M0One, 0, kE8M0One);
+            }
+            // (keeps the scheduler from sinking this chunk's products below
+            // the barrier, where they would hold two chunks of fragments)
+            __builtin_amdgcn_sched_barrier(0);
+            if (!guard || k + 1 < nk) a_store(1 - j, ra[1 - j]);
+            __syncthreads();
+        };
+        int k0 = 0;
+        using J0 = std::integral_constant<int, 0>;
+        using J1 = std::integral_constant<int, 1>;
+        for (; k0 + 3 < nk; k0 += 2) {
+            step(k0, J0{}, false);
+            step(k0 + 1, J1{}, false);
+        }
+        for (; k0 < nk; k0 += 2) {
+            step(k0, J0{}, true);
+            if (k0 + 1 < nk) step(k0 + 1, J1{}, true);
+        }
+      } else {
         BRaw Bb[P][NT];
         u32x4 ra[3][NPIECE];
         // prologue: weights of chunks 0..2 in registers, 0 and 1 in LDS, 3 in flight
@@ -775,6 +831,7 @@ __global__ void __launch_bounds__(64 * WAVES, DT == DT_F32X ? 2 : 1) conv_igemm(
             if (k0 + 1 < nk) step(k0 + 1, J1{}, true);
             if (k0 + 2 < nk) step(k0 + 2, J2{}, true);
         }
+      }
     }
     if constexpr (kALdsX) {
         // Split-FP32 weights: per chunk a row holds 32 channels x 3 parts
