@@ -179,13 +179,13 @@ __device__ __forceinline__ int xcd_logical_tile(int L, int T)
 // output tile and take interleaved K chunks; their partial sums are added in
 // LDS in the fixed wave order 0, 1, ..., KSPLIT-1, so results do not depend
 // on timing, batch size or which stream runs the kernel.
-// The split-FP32 kernels and the e4m3 GDN kernels with 8 row blocks on FP32
-// activations are built for two blocks (two waves per SIMD, 256 registers):
+// The split-FP32 kernels and the e4m3 GDN kernels on e4m3 activations are
+// built for two blocks (two waves per SIMD, 256 registers):
 // without the bound the compiler's split between VGPRs and accumulation
 // registers would take more than 256 in total.
 template <int TAG, int CIN, int MT, int NT, int WAVES, int KSPLIT, int LD, int EP, int DT>
 __global__ void __launch_bounds__(64 * WAVES,
-                                  DT == DT_F32X || (DT == DT_FP8 && WAVES == 4 && KSPLIT == 1 && MT <= 8 && LD == LD_F32) ? 2 : 1)
+                                  DT == DT_F32X || (DT == DT_FP8 && WAVES == 4 && KSPLIT == 1 && MT <= 12 && LD == LD_F32) ? 2 : 1)
 conv_igemm(ConvArgs a)
 {
     using Frag = typename Prec<DT>::Frag;
@@ -244,10 +244,10 @@ conv_igemm(ConvArgs a)
     // (GDN blocks of four unsplit waves keep idle waves: they take part in the
     // barriers of the shared weight and gamma staging)
     constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
-    // (e4m3: only for e4m3 activation inputs with 8 row blocks; the symbol
-    // loader's conversion and 12 row blocks do not fit the registers)
+    // (e4m3: only for e4m3 activation inputs, 8 or 12 row blocks; the symbol
+    // loader's conversion does not fit the registers)
     constexpr bool kALdsEarly = kGLds && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0 &&
-                                (DT != DT_FP8 || (LD == LD_F32 && MT == 8));
+                                (DT != DT_FP8 || (LD == LD_F32 && (MT == 8 || MT == 12)));
     // the split-FP32 form stages the (three times larger) weight tiles of its
     // GDN layers in LDS: a 2-stage ring filled from one register set (other
     // shapes would load them per wave)
