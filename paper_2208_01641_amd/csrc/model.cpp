@@ -426,10 +426,11 @@ int Codec::build_layers(const ParamMap& P)
         const bool is_gags = sp.id <= LIC_GA3 || (sp.id >= LIC_GS0 && sp.id <= LIC_GS3);
         L.dt = !is_gags ? DT_F32 : cfg.precision == LIC_PREC_BF16 ? DT_BF16 : cfg.precision == LIC_PREC_FP8 ? DT_FP8 : DT_F32;
         // the e4m3 form's image layer: bf16 operands (a K of 75 is one
-        // chunk; pixel values keep 8 bits), e4m3 activations out
-        // (so does the context model's first g_s layer, whose input y_hat =
-        // sym + mean arrives as bf16)
-        L.out_e4m3 = L.dt == DT_FP8 && (sp.ld == LD_RGB || (kind == 2 && sp.id == LIC_GS0));
+        // chunk; pixel values keep 8 bits), e4m3 activations out; so does
+        // g_s's first layer (its symbol loader's conversion to e4m3 does not
+        // fit two waves per SIMD, the bf16 kernel does; the context model's
+        // y_hat = sym + mean arrives as bf16 anyway)
+        L.out_e4m3 = L.dt == DT_FP8 && (sp.ld == LD_RGB || sp.id == LIC_GS0);
         if (L.out_e4m3) L.dt = DT_BF16;
         // and its output layer too (bf16 halo tiles: the 3 output channels
         // make a K chunk of 128 (tap, channel) pairs a poor fit), fed by a

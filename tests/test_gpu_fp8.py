@@ -127,13 +127,15 @@ def test_fp8_synthesis_layers(torch_dev, N, M, H, W):
     d = layer_out_shape("GA3", H, W, N, M)
     sym = np.clip(np.rint(rng.normal(0, 1.5, (M, d[0], d[1]))), -64, 64).astype(np.int8)
     prev = torch.from_numpy(np.ascontiguousarray(np.transpose(sym, (1, 2, 0)))[None]).cuda()
-    src = e4m3(sym.astype(np.float64))
+    src = sym.astype(np.float64)            # exact on the first layer's bf16 operands
     for i, L in ((0, "GS0"), (1, "GS1"), (2, "GS2")):
         # GS2 stores bf16 (the output layer's operands), the others e4m3
         o = torch.empty((1,) + layer_out_shape(L, H, W, N, M), device="cuda",
                         dtype=torch.bfloat16 if L == "GS2" else torch.uint8)
         c.run_layer(L, 1, H, W, prev, o)
-        ref = oracle.gdn(oracle.deconv2d(src, w_fp8(P[f"gs{i}.w"], "deconv"), P[f"gs{i}.b"], 2, 2, 1),
+        # (the first layer runs on bf16 operands and stores e4m3)
+        w = bf16(P["gs0.w"]) if i == 0 else w_fp8(P[f"gs{i}.w"], "deconv")
+        ref = oracle.gdn(oracle.deconv2d(src, w, P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
         if L == "GS2":
             assert rel_err(chw_any(o), ref) < BF16_OUT_TOL, L

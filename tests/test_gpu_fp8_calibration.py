@@ -15,7 +15,7 @@ import pytest
 import oracle
 import synth
 from gpu_util import chw, layer_out_shape, rel_err
-from test_gpu_fp8 import FP8_OUT_TOL, e4m3, e4m3_decode, w_fp8
+from test_gpu_fp8 import FP8_OUT_TOL, e4m3_decode, w_fp8
 from test_gpu_precision import BF16_OUT_TOL, bf16, chw_any
 
 pytestmark = pytest.mark.gpu
@@ -90,9 +90,10 @@ def test_calibration_removes_clamping_and_keeps_parity():
     assert all(q[i] > 0 for i in ids) and q[12] == 0.0 and q[13] == 0.0
     assert q[10] < 8.0                      # the enlarged layer needs a smaller scale
     o = _synthesis(c, sym)
-    src = e4m3(np.transpose(sym[0].cpu().numpy(), (2, 0, 1)).astype(np.float64))
+    src = np.transpose(sym[0].cpu().numpy(), (2, 0, 1)).astype(np.float64)
     for i, L in enumerate(("GS0", "GS1", "GS2")):
-        ref = oracle.gdn(oracle.deconv2d(src, w_fp8(P[f"gs{i}.w"], "deconv"), P[f"gs{i}.b"], 2, 2, 1),
+        w = bf16(P["gs0.w"]) if i == 0 else w_fp8(P[f"gs{i}.w"], "deconv")    # first layer: bf16 operands
+        ref = oracle.gdn(oracle.deconv2d(src, w, P[f"gs{i}.b"], 2, 2, 1),
                          P[f"gs{i}.beta"], P[f"gs{i}.gamma"], inverse=True)
         got = chw_any(o[L]) if L == "GS2" else _act(o[L], q[10 + i])
         err = rel_err(got, ref)
