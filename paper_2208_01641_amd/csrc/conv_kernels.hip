@@ -216,7 +216,7 @@ conv_igemm(ConvArgs a)
     static_assert(EP != EP_MASK || DT == DT_F32, "gradients are FP32");
     constexpr int PIXW = WAVES / KSPLIT;           // waves with distinct pixel groups
     const int lane = threadIdx.x & 63;
-    const int wave = threadIdx.x >> 6;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);     // uniform: scalar registers
     const int l16 = lane & 15;
     const int kg = lane >> 4;
 
@@ -300,8 +300,13 @@ conv_igemm(ConvArgs a)
     f4 acc[MT][NT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
+        // (loaded by every wave and selected: a load on one path only would
+        // make the K loop's wait counts conservative)
         f4 b = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (DT != DT_FP8 && kslot == 0) b = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
+        if constexpr (DT != DT_FP8) {
+            const f4 bl = *reinterpret_cast<const f4*>(a.bias + co0 + mt * 16 + kg * 4);
+            if (kslot == 0) b = bl;
+        }
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = b;
     }
@@ -611,6 +616,11 @@ conv_igemm(ConvArgs a)
     // come in exactly the cursor's order.
     constexpr bool kCursor = DT != DT_FP8 && LD != LD_RGB;
     int cur_t = kslot % ntaps, cur_kc = kslot / ntaps;
+    // one step of the cursor (KSPLIT chunks) as whole channel slices plus
+    // taps, so a step needs one compare and no loop: a loop between the
+    // loads of the ring and their use makes the compiler's wait counts
+    // conservative (it then waits for every chunk in flight but the newest)
+    const int adv_kc = KSPLIT / ntaps, adv_t = KSPLIT - adv_kc * ntaps;
     // (the tap offset is the same for every lane: dy, dx come from readlane,
     // so it stays on the scalar unit)
     long toff = 0;                                                   // tap offset in elements
@@ -621,7 +631,8 @@ conv_igemm(ConvArgs a)
         toff = ((long)dy * a.Win + dx) * CIN;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt)
-            pok[nt] = pv[nt] && (unsigned)(oy0[nt] + dy) < (unsigned)a.Hin && (unsigned)(ox0[nt] + dx) < (unsigned)a.Win;
+            // (bitwise and: no branch, so the loop stays one block)
+            pok[nt] = pv[nt] & ((unsigned)(oy0[nt] + dy) < (unsigned)a.Hin) & ((unsigned)(ox0[nt] + dx) < (unsigned)a.Win);
     };
     if constexpr (kCursor) set_tap(cur_t);
     auto cursor_loadB = [&](BRaw (&B)[NT]) __attribute__((always_inline)) {
@@ -649,8 +660,9 @@ conv_igemm(ConvArgs a)
                 B[nt] = *reinterpret_cast<const BIn*>(src);
             }
         }
-        cur_t += KSPLIT;
-        while (cur_t >= ntaps) {
+        cur_t += adv_t;
+        cur_kc += adv_kc;
+        if (cur_t >= ntaps) {
             cur_t -= ntaps;
             ++cur_kc;
         }
@@ -1042,18 +1054,29 @@ conv_igemm(ConvArgs a)
     Frag Ab[(kALds || kALdsX || kTile) ? 1 : P][MT];
     BRaw Bb[(kALds || kALdsX || kTile) ? 1 : P][NT];
     if constexpr (!kALds && !kALdsX && !kTile) {
-#pragma unroll
-    for (int j = 0; j < P - 1; ++j)
-        if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
     // steady state: every step issues its prefetch unconditionally, so the
-    // wait before a chunk's MFMAs only covers that chunk's own loads
+    // wait before a chunk's MFMAs only covers that chunk's own loads.  The
+    // prologue before it is unconditional too: a load that some path skips
+    // makes the compiler's wait counts at the loop head count from that path
+    // (it then waits for every chunk in flight)
     int k0 = 0;
-    for (; k0 + 2 * P - 2 < nk; k0 += P) {
+    if (2 * P - 2 < nk) {
 #pragma unroll
-        for (int j = 0; j < P; ++j) {
-            load(kslot + (k0 + j + P - 1) * KSPLIT, Ab[(j + P - 1) % P], Bb[(j + P - 1) % P]);
-            compute(Ab[j], Bb[j]);
+        for (int j = 0; j < P - 1; ++j) {
+            load(kslot + j * KSPLIT, Ab[j], Bb[j]);
+            __builtin_amdgcn_sched_barrier(0);          // chunks issued in order, oldest first
         }
+        for (; k0 + 2 * P - 2 < nk; k0 += P) {
+#pragma unroll
+            for (int j = 0; j < P; ++j) {
+                load(kslot + (k0 + j + P - 1) * KSPLIT, Ab[(j + P - 1) % P], Bb[(j + P - 1) % P]);
+                compute(Ab[j], Bb[j]);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int j = 0; j < P - 1; ++j)
+            if (j < nk) load(kslot + j * KSPLIT, Ab[j], Bb[j]);
     }
     for (; k0 < nk; k0 += P) {
 #pragma unroll
