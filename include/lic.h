@@ -72,7 +72,9 @@ typedef struct {
     int32_t  precision;        /* LIC_PREC_FP32, _BF16 or _FP8: g_a / g_s GEMM       */
                                /* operands and their activations in bf16, or in OCP  */
                                /* e4m3 with per-output-channel FP32 weight scales    */
-                               /* and a fixed activation scale (FP32 accumulation;   */
+                               /* and per-layer activation scales (codec_calibrate;  */
+                               /* the image layer, g_s's first and last layers run   */
+                               /* on bf16 operands in that form; FP32 accumulation;  */
                                /* GDN/IGDN normaliser from three bf16 part products, */
                                /* about 2^-16 relative, normalisation in FP32);      */
                                /* h_a, h_s, the quantisers and the scale index stay  */
