@@ -207,6 +207,7 @@ def test_layer_kernel_forms(torch_dev):
     assert c.layer_kernel("GA1", 720, 1280) == ("fp8", 1)
     assert c.layer_kernel("GS2", 720, 1280) == ("fp8", 1)
     assert c.layer_kernel("GA0", 720, 1280) == ("bf16", 1)    # image layer: bf16 operands
+    assert c.layer_kernel("GS0", 720, 1280) == ("bf16", 1)    # g_s's first layer: bf16 operands
     assert c.layer_kernel("GS3", 720, 1280) == ("bf16", 1)    # output layer: bf16 halo tiles
     # GS2 stores bf16 for it; the other GDN layers e4m3 bytes
     n_px = 384 * 640 * 128
