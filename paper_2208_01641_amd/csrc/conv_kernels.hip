@@ -110,7 +110,9 @@ template <> struct Prec<DT_F32X> {
 //            chunks of 128: lane group g takes 32 consecutive channels of one
 //            tap (channels per tap are a multiple of 32).  Weights carry a
 //            per-row FP32 scale and activations are stored as e4m3(q x) with
-//            a fixed per-layer q, both undone in the epilogue.
+//            a per-layer q, both undone in the epilogue; the operands come
+//            from e4m3 activations only (the image layer and g_s's first and
+//            last layers of that form run on bf16 operands).
 template <> struct Prec<DT_FP8> {
     using Frag = i32x8;
     using Elem = uint8_t;
@@ -244,8 +246,7 @@ conv_igemm(ConvArgs a)
     // (GDN blocks of four unsplit waves keep idle waves: they take part in the
     // barriers of the shared weight and gamma staging)
     constexpr bool kGLds = KSPLIT == 1 && WAVES == 4 && (EP == EP_GDN || EP == EP_IGDN);
-    // (e4m3: only for e4m3 activation inputs, 8 or 12 row blocks; the symbol
-    // loader's conversion does not fit the registers)
+    // (e4m3: 8 or 12 row blocks)
     constexpr bool kALdsEarly = kGLds && DT != DT_F32X && LD != LD_RGB && MT % 4 == 0 &&
                                 (DT != DT_FP8 || (LD == LD_F32 && (MT == 8 || MT == 12)));
     // the split-FP32 form stages the (three times larger) weight tiles of its
@@ -502,72 +503,22 @@ conv_igemm(ConvArgs a)
             A[mt] = *reinterpret_cast<const Frag*>(src);
         }
     };
-    auto pack4 = [](float v0, float v1, float v2, float v3) -> int {
-        return (int)(e4m3x2(v0, v1) | (e4m3x2(v2, v3) << 16));
-    };
+    // (e4m3 operands come only from e4m3 activations: the image layer and
+    // g_s's first and last layers run on bf16 operands in that form)
+    static_assert(DT != DT_FP8 || LD == LD_F32, "e4m3 operands load e4m3 activations only");
     auto loadB8 = [&](int kc, Frag (&B)[NT]) __attribute__((always_inline)) {
       if constexpr (DT == DT_FP8) {
         const int f = kc * KCH + kg * KE;
         const int t = f / CIN, c = f - (f / CIN) * CIN;
+        const int tv = __builtin_amdgcn_ds_bpermute(4 * (t < ntaps ? t : 0), tapv);
+        const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) {
-            Frag v = {};
-            if constexpr (LD == LD_RGB) {
-                // flattened (tap, channel) pairs of the 3-channel NCHW input
-                const float* in = static_cast<const float*>(a.in);
-                const int kk = a.kk, kn = 3 * a.kk * a.kk;
-                // walk (u, w, ch) incrementally from k = c: no division per element
-                int tap = c / 3, ch = c - 3 * (c / 3);
-                int u = tap / kk, w = tap - kk * (tap / kk);
-                const long plane = (long)a.Hin * a.Win;
-                const float* base = in + (long)img[nt] * 3 * plane;
-#pragma unroll
-                for (int q = 0; q < 8; ++q) {
-                    float x4[4];
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int k = c + 4 * q + i;
-                        const int iy = gy[nt] * a.s_in + u - a.pad, ix = gx[nt] * a.s_in + w - a.pad;
-                        const bool ok = pv[nt] && t < ntaps && k < kn && iy >= 0 && iy < a.Hin && ix >= 0 && ix < a.Win;
-                        x4[i] = ok ? base[ch * plane + (long)iy * a.Win + ix] : 0.0f;
-                        if (++ch == 3) {
-                            ch = 0;
-                            if (++w == kk) {
-                                w = 0;
-                                ++u;
-                            }
-                        }
-                    }
-                    v[q] = pack4(x4[0], x4[1], x4[2], x4[3]);
-                }
-            } else {
-                const int tv = __builtin_amdgcn_ds_bpermute(4 * (t < ntaps ? t : 0), tapv);
-                const int dy = (int)(short)(tv & 0xffff), dx = tv >> 16;
-                const bool ok = t < ntaps && pv[nt] && (unsigned)(oy0[nt] + dy) < (unsigned)a.Hin &&
-                                (unsigned)(ox0[nt] + dx) < (unsigned)a.Win;
-                const int off = (dy * a.Win + dx) * CIN + c;              // from the window origin
-                {
-                    if constexpr (LD == LD_I8) {
-                        // y_hat = symbol + offset, rounded to e4m3 (exact for |y_hat| <= 16)
-                        const int8_t* src = ok ? reinterpret_cast<const int8_t*>(pbase[nt]) + off
-                                               : static_cast<const int8_t*>(a.zero);
-                        const float* mu = ok ? a.mu_in + c : static_cast<const float*>(a.zero);
-                        const uint4 u0 = *reinterpret_cast<const uint4*>(src);
-                        const uint4 u1 = *reinterpret_cast<const uint4*>(src + 16);
-                        const uint32_t w[8] = {u0.x, u0.y, u0.z, u0.w, u1.x, u1.y, u1.z, u1.w};
-#pragma unroll
-                        for (int q = 0; q < 8; ++q)
-                            v[q] = pack4((float)(int8_t)(w[q]) + mu[4 * q], (float)(int8_t)(w[q] >> 8) + mu[4 * q + 1],
-                                         (float)(int8_t)(w[q] >> 16) + mu[4 * q + 2],
-                                         (float)(int8_t)(w[q] >> 24) + mu[4 * q + 3]);
-                    } else {
-                        const Elem* src = ok ? reinterpret_cast<const Elem*>(pbase[nt]) + off
-                                             : static_cast<const Elem*>(a.zero);
-                        v = *reinterpret_cast<const Frag*>(src);
-                    }
-                }
-            }
-            B[nt] = v;
+            const bool ok = t < ntaps && pv[nt] && (unsigned)(oy0[nt] + dy) < (unsigned)a.Hin &&
+                            (unsigned)(ox0[nt] + dx) < (unsigned)a.Win;
+            const int off = (dy * a.Win + dx) * CIN + c;              // from the window origin
+            const Elem* src = ok ? reinterpret_cast<const Elem*>(pbase[nt]) + off : static_cast<const Elem*>(a.zero);
+            B[nt] = *reinterpret_cast<const Frag*>(src);
         }
       }
     };
@@ -1551,9 +1502,9 @@ static const KernelEntry kEntries[] = {
     LIC_KGF(LIC_GA1, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA1, 192, 12, 1, LD_F32, EP_GDN),
     LIC_KGF(LIC_GA2, 128, 8, 2, LD_F32, EP_GDN), LIC_KGF(LIC_GA2, 192, 12, 1, LD_F32, EP_GDN),
     // one 16-pixel group per wave (grids between half and one wave per SIMD)
-    LIC_KF(LIC_GA2, 128, 8, 1, 4, LD_F32, EP_GDN), LIC_KF(LIC_GS0, 192, 8, 1, 4, LD_I8, EP_IGDN),
+    LIC_KF(LIC_GA2, 128, 8, 1, 4, LD_F32, EP_GDN),
     LIC_K2F(LIC_GA3, 128, LD_F32, EP_QUANT), LIC_K2F(LIC_GA3, 192, LD_F32, EP_QUANT),
-    LIC_KGF(LIC_GS0, 192, 8, 2, LD_I8, EP_IGDN), LIC_KGF(LIC_GS0, 320, 12, 1, LD_I8, EP_IGDN),
+    // (g_s's first layer runs on bf16 operands in this form: no e4m3 kernel)
     LIC_KGF(LIC_GS1, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS1, 192, 12, 1, LD_F32, EP_IGDN),
     LIC_KGF(LIC_GS2, 128, 8, 2, LD_F32, EP_IGDN), LIC_KGF(LIC_GS2, 192, 12, 1, LD_F32, EP_IGDN),
     // distilled synthesis network (64 hidden channels): forward in FP32 or
