@@ -520,6 +520,9 @@ def main():
     ap.add_argument("--rans-lanes", type=int, default=8,
                     help="entropy coder: interleaved rANS states (0: byte-wise single-state rANS)")
     ap.add_argument("--serial", action="store_true", help="one frame in flight (unpipelined)")
+    ap.add_argument("--channels", choices=["128x192", "192x320"], default="128x192",
+                    help="N x M of the main workload's codec")
+    ap.add_argument("--batch", type=int, default=1, help="frames per codec task of the main workload")
     ap.add_argument("--kind", type=int, choices=[0, 1, 2], default=1,
                     help="codec of the main workload: 1 scale hyperprior (the metric's), 0 factorized prior, "
                          "2 context model (for profiles of those codecs)")
@@ -552,14 +555,14 @@ def main():
     prec = {"fp32": 0, "bf16": 1, "fp8": 2}[args.precision]
     dtype = {0: "f32", 1: "bf16", 2: "fp8"}[prec]
     H, W, K, Wm = args.height, args.width, args.steps, args.warmup
-    N, M = 128, 192
+    N, M = (int(v) for v in args.channels.split("x"))
     # (the headline run times two layers only: events between every launch
     # perturb the pipelined run; the one-frame-in-flight variant times all)
     timed = ["GA1", "GS2"]
     if args.all_layers:
         timed = [L for L in LAYERS if args.kind or not L.startswith("H")] + (list(CTX_LAYERS) if args.kind == 2 else [])
     main_res, x0, P, blob = run_workload(
-        H=H, W=W, N=N, M=M, precision=prec, batch=1, steps=K, warmup=Wm, threads=threads,
+        H=H, W=W, N=N, M=M, precision=prec, batch=args.batch, steps=K, warmup=Wm, threads=threads,
         inflight=1 if args.serial else args.inflight, slices=args.slices, zero_copy=args.zero_copy,
         timed_layers=timed, copy_probe_mib=args.copy_probe_mib, kind=args.kind)
 
@@ -571,7 +574,7 @@ def main():
     roofline = {"bound": "mfma", "achieved": round(ach, 2), "peak": peak, "unit": "TFLOP/s",
                 "frac": round(ach / peak, 4),
                 "traffic": (traffic_for(dom, args.precision)
-                            if (H, W, N, M, args.kind) == (720, 1280, 128, 192, 1) else None),
+                            if (H, W, N, M, args.kind, args.batch) == (720, 1280, 128, 192, 1, 1) else None),
                 "kernel": dom, "form": form, "peak_basis": PEAK_BASIS[form],
                 "avg_us": round(per_layer[dom]["avg_us"], 2),
                 "flops_per_launch": per_layer[dom]["flops_per_launch"]}
@@ -590,7 +593,8 @@ def main():
         "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": f"{CODEC_NAME[args.kind]} N={N} M={M} {args.precision.upper()} encode chained into decode, "
-                               f"3x{H}x{W} frames (32 moving sinusoids + noise), pipelined",
+                               f"3x{H}x{W} frames (32 moving sinusoids + noise)"
+                               + (f", batches of {args.batch}" if args.batch > 1 else "") + ", pipelined",
                    "frames": K, "entropy_threads": threads, "max_in_flight": 1 if args.serial else args.inflight,
                    "y_slices": args.slices, "zero_copy": args.zero_copy, "rans_lanes": args.rans_lanes},
         "p50_ms": round(main_res["p50_ms"], 3),
